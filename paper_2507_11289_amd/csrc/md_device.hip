@@ -1,0 +1,961 @@
+// md_device.hip -- gfx950 kernels of the slice-streaming Lennard-Jones path.
+//
+// Paper: "Cyclic Data Streaming on GPUs for Short Range Stencils Applied to
+// Molecular Dynamics" (arXiv 2507.11289).
+//   * Sec. 4: truncated-and-shifted LJ 12-6 (sigma = epsilon = 1), cells of edge > rc,
+//     neighbours in the own and adjacent cells, input/output order 1 in x.
+//   * Algorithm 1: pair force F_abs = 24 (2 r^-12 - r^-6) / r^2 on r_ij for
+//     r_ij . r_ij <= rc^2, energy and virial accumulation, velocity-Verlet update.
+//   * Sec. 4.1: molecules processed in cell order so that neighbouring lanes share
+//     neighbour lists (md_fill_mol_work_list / md_v3a); new velocities (md_v3aa);
+//     energy/virial collection (stat_collect); new positions and the runtime decision
+//     in which slice a molecule is stored (md_v3b).
+//   * Sec. 3.1-3.3 / Table 1: a slice is processed once its neighbours are present; on
+//     one GPU this becomes a persistent kernel whose work items wait on per-slice
+//     counters (slice i advances t -> t+1 once i-1 and i+1 reached t).
+//
+// One wavefront owns one cell at a time.  A cell's atoms sit in slots 0..n-1 of its
+// 64-slot block, ordered by id, so the force sum of every atom has a fixed order and
+// the whole trajectory is bitwise independent of the claim order of the work items.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "md_internal.h"
+
+namespace mdk {
+
+constexpr int TILE = 256;  // neighbour candidates staged in LDS per pass
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double* cblk(unsigned char* base, int c) {
+  return reinterpret_cast<double*>(base + (size_t)c * CELL_BYTES);
+}
+__device__ __forceinline__ const double* cblk(const unsigned char* base, int c) {
+  return reinterpret_cast<const double*>(base + (size_t)c * CELL_BYTES);
+}
+__device__ __forceinline__ uint32_t* cids(double* b) {
+  return reinterpret_cast<uint32_t*>(b + CELL_DOUBLES);
+}
+__device__ __forceinline__ const uint32_t* cids(const double* b) {
+  return reinterpret_cast<const uint32_t*>(b + CELL_DOUBLES);
+}
+
+__device__ __forceinline__ unsigned ld_acquire(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void raise_error(uint32_t* err, uint32_t* abort_flag, uint32_t bits) {
+  __hip_atomic_fetch_or(err, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (abort_flag) __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Cell coordinate along one axis: floor(x * (1/l)) with one IEEE multiply, clamped
+// to [0, G-1] (a coordinate equal to L after wrapping belongs to the last cell).
+__device__ __forceinline__ int coord_cell(double x, double inv_l, int G) {
+  double f = floor(__dmul_rn(x, inv_l));
+  if (!(f >= 0.0)) return 0;
+  if (f > (double)(G - 1)) return G - 1;
+  return (int)f;
+}
+
+__device__ __forceinline__ int global_cell(const DGeom& g, int gx, int gy, int gz) {
+  int s = gx / g.ncx;
+  return s * g.cps + ((gx - s * g.ncx) * g.G[1] + gy) * g.G[2] + gz;
+}
+
+__device__ __forceinline__ void cell_xyz(const DGeom& g, int c, int& gx, int& gy, int& gz) {
+  int s = c / g.cps;
+  int local = c - s * g.cps;
+  gz = local % g.G[2];
+  int t = local / g.G[2];
+  gy = t % g.G[1];
+  gx = s * g.ncx + t / g.G[1];
+}
+
+// Minimum image of one component (the box is at least 3 cells, so the image within
+// rc is unique).
+__device__ __forceinline__ double min_img(double d, double L, double h) {
+  return d > h ? __dsub_rn(d, L) : (d < -h ? __dadd_rn(d, L) : d);
+}
+
+__device__ __forceinline__ double r2_exact(double dx, double dy, double dz) {
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+__device__ __forceinline__ double wrap1(double x, double L) {
+  return x >= L ? __dsub_rn(x, L) : (x < 0.0 ? __dadd_rn(x, L) : x);
+}
+
+// ---------------------------------------------------------------------------
+// per-wave LDS scratch
+// ---------------------------------------------------------------------------
+template <int PREC> struct Scratch;
+template <> struct Scratch<1> {  // FP32 pair math: cell-relative FP32 positions + tag
+  int nb_cell[28];
+  int nb_pre[28];
+  union {
+    float4 q[TILE];
+    double red[64 * 6];
+  };
+};
+template <> struct Scratch<0> {  // FP64 pair math: raw FP64 positions + tag
+  int nb_cell[28];
+  int nb_pre[28];
+  union {
+    struct {
+      double x[TILE], y[TILE], z[TILE];
+    } t;
+    double red[64 * 6];
+  };
+  uint32_t tag[TILE];
+};
+
+struct ForceOut {
+  double fx, fy, fz;  // force on the lane's atom (lanes < n)
+  double uh, wh;      // half sums of pair energy / pair virial
+  unsigned pc;        // in-range partners (count mode)
+  int n;              // atoms in the cell (uniform)
+  int total;          // candidates in the 27 cells, self included (uniform)
+};
+
+// Candidate (m, k): neighbour m in 0..26, slot k.  m = (ox+1)*9 + (oy+1)*3 + (oz+1).
+__device__ __forceinline__ unsigned make_tag(int m, int k) { return ((unsigned)m << 6) | (unsigned)k; }
+
+// Exact FP64 in-range decision for a pair whose FP32 r^2 fell in the guard band.
+__device__ __noinline__ bool exact_in_range(const DGeom& g, double xi, double yi, double zi,
+                                            const unsigned char* cells, int nc, int k) {
+  const double* jb = cblk(cells, nc);
+  double dx = min_img(__dsub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
+  double dy = min_img(__dsub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
+  double dz = min_img(__dsub_rn(zi, jb[2 * CELL_CAP + k]), g.L[2], g.halfL[2]);
+  return r2_exact(dx, dy, dz) <= g.rc2;
+}
+
+// ---------------------------------------------------------------------------
+// Pair forces of every atom of cell c (Algorithm 1, first loop; kernel md_v3a).
+// Lane layout: P = n atoms x G groups (G = min(16, 64 / n)); lane (ii, grp) sums the
+// candidates grp, grp + G, ... of the 27-cell list for atom ii; the group partials are
+// then added in group order, so every atom's sum has a fixed order.
+// ---------------------------------------------------------------------------
+template <int PREC, bool ENERGY, bool COUNT>
+__device__ void cell_force(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt,
+                           int c, Scratch<PREC>& ws, ForceOut& o) {
+  const int lane = __lane_id();
+  const int n_i = (int)ncnt[c];
+  o.n = n_i;
+  o.fx = o.fy = o.fz = 0.0;
+  o.uh = o.wh = 0.0;
+  o.pc = 0;
+  o.total = 0;
+  if (n_i == 0) return;
+
+  int gx, gy, gz;
+  cell_xyz(g, c, gx, gy, gz);
+
+  // neighbour table: lane m < 27 handles neighbour m
+  int cnt = 0, nc = 0;
+  bool wrapped = false;
+  if (lane < 27) {
+    int nx = gx + lane / 9 - 1, ny = gy + (lane / 3) % 3 - 1, nz = gz + lane % 3 - 1;
+    wrapped = nx < 0 || nx >= g.G[0] || ny < 0 || ny >= g.G[1] || nz < 0 || nz >= g.G[2];
+    nx += nx < 0 ? g.G[0] : (nx >= g.G[0] ? -g.G[0] : 0);
+    ny += ny < 0 ? g.G[1] : (ny >= g.G[1] ? -g.G[1] : 0);
+    nz += nz < 0 ? g.G[2] : (nz >= g.G[2] ? -g.G[2] : 0);
+    nc = global_cell(g, nx, ny, nz);
+    cnt = (int)ncnt[nc];
+  }
+  int incl = cnt;
+#pragma unroll
+  for (int off = 1; off < 32; off <<= 1) {
+    int v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  const int total = __shfl(incl, 26);
+  const bool any_wrap = __ballot(wrapped) != 0ull;
+  wave_sync();
+  if (lane < 27) {
+    ws.nb_cell[lane] = nc;
+    ws.nb_pre[lane] = incl - cnt;
+  }
+  if (lane == 0) ws.nb_pre[27] = total;
+  wave_sync();
+  o.total = total;
+
+  const int P = n_i;
+  int G = 64 / P;
+  if (G > 16) G = 16;
+  const int ii = lane % P;
+  const int grp = lane / P;
+  const bool act = grp < G;
+  const double* ib = cblk(cells, c);
+  const double xi = ib[ii], yi = ib[CELL_CAP + ii], zi = ib[2 * CELL_CAP + ii];
+  const unsigned selftag = make_tag(13, ii);
+
+  double uacc = 0.0, wacc = 0.0;
+  unsigned pc = 0;
+  double sfx, sfy, sfz;
+
+  if constexpr (PREC == 1) {
+    // FP32 on coordinates relative to the cell's lower corner (|q| < 2 cells).
+    const double ox = gx * g.l[0], oy = gy * g.l[1], oz = gz * g.l[2];
+    const float qix = (float)(xi - ox), qiy = (float)(yi - oy), qiz = (float)(zi - oz);
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    for (int tb = 0; tb < total; tb += TILE) {
+      const int tn = min(TILE, total - tb);
+      wave_sync();
+      for (int e = lane; e < tn; e += 64) {
+        const int f = tb + e;
+        int lo = 0, hi = 27;
+        while (hi - lo > 1) {
+          int mid = (lo + hi) >> 1;
+          if (ws.nb_pre[mid] <= f) lo = mid; else hi = mid;
+        }
+        const int k = f - ws.nb_pre[lo];
+        const double* jb = cblk(cells, ws.nb_cell[lo]);
+        const int nx = gx + lo / 9 - 1, ny = gy + (lo / 3) % 3 - 1, nz = gz + lo % 3 - 1;
+        const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
+        const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
+        const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
+        float4 q;
+        q.x = (float)((jb[k] + shx) - ox);
+        q.y = (float)((jb[CELL_CAP + k] + shy) - oy);
+        q.z = (float)((jb[2 * CELL_CAP + k] + shz) - oz);
+        q.w = __uint_as_float(make_tag(lo, k));
+        ws.q[e] = q;
+      }
+      wave_sync();
+      for (int f = act ? grp : tn; f < tn; f += G) {
+        const float4 q = ws.q[f];
+        const float dx = qix - q.x, dy = qiy - q.y, dz = qiz - q.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const unsigned tag = __float_as_uint(q.w);
+        if (r2 <= g.rc2_hi_f && tag != selftag) {
+          bool inr = r2 <= g.rc2_lo_f;
+          if (!inr) inr = exact_in_range(g, xi, yi, zi, cells, ws.nb_cell[tag >> 6], tag & 63u);
+          if (inr) {
+            const float ir2 = __builtin_amdgcn_rcpf(r2);
+            const float ir6 = ir2 * ir2 * ir2;
+            const float t = 2.0f * ir6 - 1.0f;
+            const float fr = 24.0f * ir2 * ir6 * t;
+            fx += fr * dx;
+            fy += fr * dy;
+            fz += fr * dz;
+            if (ENERGY) {
+              uacc += (double)(4.0f * ir6 * (ir6 - 1.0f) - g.uc_f);
+              wacc += (double)(24.0f * ir6 * t);
+            }
+            if (COUNT) pc++;
+          }
+        }
+      }
+    }
+    sfx = fx;
+    sfy = fy;
+    sfz = fz;
+  } else {
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int tb = 0; tb < total; tb += TILE) {
+      const int tn = min(TILE, total - tb);
+      wave_sync();
+      for (int e = lane; e < tn; e += 64) {
+        const int f = tb + e;
+        int lo = 0, hi = 27;
+        while (hi - lo > 1) {
+          int mid = (lo + hi) >> 1;
+          if (ws.nb_pre[mid] <= f) lo = mid; else hi = mid;
+        }
+        const int k = f - ws.nb_pre[lo];
+        const double* jb = cblk(cells, ws.nb_cell[lo]);
+        ws.t.x[e] = jb[k];
+        ws.t.y[e] = jb[CELL_CAP + k];
+        ws.t.z[e] = jb[2 * CELL_CAP + k];
+        ws.tag[e] = make_tag(lo, k);
+      }
+      wave_sync();
+      if (!any_wrap) {
+        // no periodic neighbour: the raw difference is the minimum image of every
+        // pair that can be in range
+        for (int f = act ? grp : tn; f < tn; f += G) {
+          const double dx = __dsub_rn(xi, ws.t.x[f]);
+          const double dy = __dsub_rn(yi, ws.t.y[f]);
+          const double dz = __dsub_rn(zi, ws.t.z[f]);
+          const double r2 = r2_exact(dx, dy, dz);
+          if (r2 <= g.rc2 && ws.tag[f] != selftag) {
+            const double ir2 = 1.0 / r2;
+            const double ir6 = ir2 * ir2 * ir2;
+            const double t = 2.0 * ir6 - 1.0;
+            const double fr = 24.0 * ir2 * ir6 * t;
+            fx += fr * dx;
+            fy += fr * dy;
+            fz += fr * dz;
+            if (ENERGY) {
+              uacc += 4.0 * ir6 * (ir6 - 1.0) - g.uc;
+              wacc += 24.0 * ir6 * t;
+            }
+            if (COUNT) pc++;
+          }
+        }
+      } else {
+        for (int f = act ? grp : tn; f < tn; f += G) {
+          const double dx = min_img(__dsub_rn(xi, ws.t.x[f]), g.L[0], g.halfL[0]);
+          const double dy = min_img(__dsub_rn(yi, ws.t.y[f]), g.L[1], g.halfL[1]);
+          const double dz = min_img(__dsub_rn(zi, ws.t.z[f]), g.L[2], g.halfL[2]);
+          const double r2 = r2_exact(dx, dy, dz);
+          if (r2 <= g.rc2 && ws.tag[f] != selftag) {
+            const double ir2 = 1.0 / r2;
+            const double ir6 = ir2 * ir2 * ir2;
+            const double t = 2.0 * ir6 - 1.0;
+            const double fr = 24.0 * ir2 * ir6 * t;
+            fx += fr * dx;
+            fy += fr * dy;
+            fz += fr * dz;
+            if (ENERGY) {
+              uacc += 4.0 * ir6 * (ir6 - 1.0) - g.uc;
+              wacc += 24.0 * ir6 * t;
+            }
+            if (COUNT) pc++;
+          }
+        }
+      }
+    }
+    sfx = fx;
+    sfy = fy;
+    sfz = fz;
+  }
+
+  // add the group partials of each atom in group order
+  wave_sync();
+  double* red = ws.red;
+  red[lane * 6 + 0] = sfx;
+  red[lane * 6 + 1] = sfy;
+  red[lane * 6 + 2] = sfz;
+  red[lane * 6 + 3] = uacc;
+  red[lane * 6 + 4] = wacc;
+  red[lane * 6 + 5] = (double)pc;
+  wave_sync();
+  if (lane < P) {
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+    for (int q = 0; q < G; q++) {
+      const double* r = red + (lane + q * P) * 6;
+      a0 += r[0];
+      a1 += r[1];
+      a2 += r[2];
+      a3 += r[3];
+      a4 += r[4];
+      a5 += r[5];
+    }
+    o.fx = a0;
+    o.fy = a1;
+    o.fz = a2;
+    o.uh = 0.5 * a3;
+    o.wh = 0.5 * a4;
+    o.pc = (unsigned)a5;
+  }
+  wave_sync();
+}
+
+// Per-item accumulators of one wave.
+struct ItemAcc {
+  double u, w, k;                 // per lane (energy steps)
+  unsigned long long cand, inr;   // per lane (count mode)
+  unsigned left, right;           // uniform migration counts
+};
+
+__device__ __forceinline__ void acc_zero(ItemAcc& a) {
+  a.u = a.w = a.k = 0.0;
+  a.cand = a.inr = 0;
+  a.left = a.right = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Force + velocity-Verlet + migration of one cell (kernels md_v3a, md_v3aa, md_v3b).
+// The stored velocity is the half-step velocity v(t - dt/2), or v(t) itself on the
+// first step after a load.  One step of the synchronous form:
+//   v(t) = v(t-dt/2) + (dt/2) F(t);  v(t+dt/2) = v(t) + (dt/2) F(t);
+//   r(t+dt) = r(t) + dt v(t+dt/2), wrapped; the new cell decides where the atom is
+// stored: the same cell (kept in order), or appended to another cell -- possibly in
+// the left or right neighbour slice.
+// ---------------------------------------------------------------------------
+template <int PREC, bool ENERGY, bool COUNT>
+__device__ void p2_cell(const RunArgs& ra, int c, int src, int first, Scratch<PREC>& ws,
+                        ItemAcc& acc, uint32_t* abort_flag) {
+  const DGeom& g = ra.g;
+  ForceOut o;
+  cell_force<PREC, ENERGY, COUNT>(g, ra.cells[src], ra.ncnt[src], c, ws, o);
+  const int lane = __lane_id();
+  const int dst = src ^ 1;
+  if (o.n == 0) {
+    if (lane == 0) ra.ncnt[dst][c] = 0u;
+    return;
+  }
+  const bool own = lane < o.n;
+  const double* ib = cblk(ra.cells[src], c);
+  const int s_old = c / g.cps;
+  double xn[3] = {0, 0, 0}, vh[3] = {0, 0, 0};
+  uint32_t id = 0;
+  int dest = c;
+  uint32_t bad = 0;
+  int dir = 0;  // 0 stay in slice, 1 left, 2 right
+  if (own) {
+    const double F[3] = {o.fx, o.fy, o.fz};
+    double vf[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const double v = ib[(3 + d) * CELL_CAP + lane];
+      vf[d] = first ? v : __dadd_rn(v, __dmul_rn(g.hdt, F[d]));
+    }
+    if (ENERGY) {
+      acc.k += 0.5 * __dadd_rn(__dadd_rn(__dmul_rn(vf[0], vf[0]), __dmul_rn(vf[1], vf[1])),
+                               __dmul_rn(vf[2], vf[2]));
+      acc.u += o.uh;
+      acc.w += o.wh;
+    }
+    if (COUNT) {
+      acc.cand += (unsigned long long)(o.total - 1);
+      acc.inr += o.pc;
+    }
+    int gc[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      vh[d] = __dadd_rn(vf[d], __dmul_rn(g.hdt, F[d]));
+      const double x = __dadd_rn(ib[d * CELL_CAP + lane], __dmul_rn(g.dt, vh[d]));
+      xn[d] = wrap1(x, g.L[d]);
+      if (!isfinite(xn[d]) || !isfinite(vh[d]) || !(xn[d] >= 0.0) || xn[d] > g.L[d])
+        bad |= ERR_NONFINITE;
+      gc[d] = coord_cell(xn[d], g.inv_l[d], g.G[d]);
+    }
+    id = cids(ib)[lane];
+    dest = global_cell(g, gc[0], gc[1], gc[2]);
+    const int s_new = gc[0] / g.ncx;
+    const int delta = (s_new - s_old + g.S) % g.S;
+    if (delta == 1) dir = 2;
+    else if (delta == g.S - 1) dir = 1;
+    else if (delta != 0) bad |= ERR_DISPLACEMENT;
+  }
+  if (bad) raise_error(ra.err, abort_flag, bad);
+  const bool ok = own && !bad;
+  const bool stay = ok && dest == c;
+  const unsigned long long sm = __ballot(stay);
+  int slot = -1;
+  if (stay) {
+    slot = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(sm >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)sm, 0u));
+  } else if (ok) {
+    const unsigned old =
+        __hip_atomic_fetch_add(ra.nin[dst] + dest, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old < (unsigned)CELL_CAP) slot = CELL_CAP - 1 - (int)old;
+    else raise_error(ra.err, abort_flag, ERR_CAPACITY);
+  }
+  if (slot >= 0) {
+    double* ob = cblk(ra.cells[dst], dest);
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      ob[d * CELL_CAP + slot] = xn[d];
+      ob[(3 + d) * CELL_CAP + slot] = vh[d];
+    }
+    cids(ob)[slot] = id;
+  }
+  if (lane == 0) ra.ncnt[dst][c] = (uint32_t)__popcll(sm);
+  acc.left += (unsigned)__popcll(__ballot(ok && dir == 1));
+  acc.right += (unsigned)__popcll(__ballot(ok && dir == 2));
+}
+
+// ---------------------------------------------------------------------------
+// Order the atoms of one cell by id (wave-wide rank sort).  Entries come from slots
+// [0, n_low) and from the top slots [CAP - n_high, CAP); the result fills slots
+// [0, n_low + n_high).  Every lane reads its entry before any lane writes.
+// ---------------------------------------------------------------------------
+__device__ void cell_sort_wave(unsigned char* cells, int c, int n_low, int n_high) {
+  const int lane = __lane_id();
+  const int n = n_low + n_high;
+  double* p = cblk(cells, c);
+  uint32_t* ids = cids(p);
+  const bool act = lane < n;
+  const int from = lane < n_low ? lane : CELL_CAP - 1 - (lane - n_low);
+  double v[6];
+  uint32_t id = 0xffffffffu;
+  if (act) {
+#pragma unroll
+    for (int d = 0; d < 6; d++) v[d] = p[d * CELL_CAP + from];
+    id = ids[from];
+  }
+  int rank = 0;
+  for (int m = 0; m < n; m++) {
+    const uint32_t other = (uint32_t)__shfl((int)id, m);
+    rank += other < id ? 1 : 0;
+  }
+  __asm__ volatile("" ::: "memory");
+  wave_sync();
+  if (act) {
+#pragma unroll
+    for (int d = 0; d < 6; d++) p[d * CELL_CAP + rank] = v[d];
+    ids[rank] = id;
+  }
+}
+
+// Finalise the cells [b, e) of one slice for the step held in parity `dst`: append the
+// atoms that moved in, restore id order, publish the count; clear the move-in counters
+// of the other parity for the next step.
+__device__ void p1_range(const RunArgs& ra, int b, int e, int dst, int wave, uint32_t* abort_flag) {
+  const int lane = __lane_id();
+  const int src = dst ^ 1;
+  for (int base = b + wave * 64; base < e; base += WAVES * 64) {
+    const int c = base + lane;
+    unsigned n_stay = 0, n_in = 0;
+    if (c < e) {
+      n_stay = ra.ncnt[dst][c];
+      n_in = ra.nin[dst][c];
+      ra.nin[src][c] = 0u;
+      if (n_stay + n_in > (unsigned)CELL_CAP) {
+        raise_error(ra.err, abort_flag, ERR_CAPACITY);
+        n_in = 0;
+      }
+      if (n_in) ra.ncnt[dst][c] = n_stay + n_in;
+    }
+    unsigned long long dirty = __ballot(n_in != 0);
+    while (dirty) {
+      const int l = __ffsll((long long)dirty) - 1;
+      dirty &= dirty - 1;
+      const int cc = __shfl(c, l);
+      const int lo = __shfl((int)n_stay, l);
+      const int hi = __shfl((int)n_in, l);
+      cell_sort_wave(ra.cells[dst], cc, lo, hi);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent kernel: claims tickets in order; ticket -> (round k, run, item); an item
+// waits on the per-slice counters of its two neighbours and itself, runs, publishes.
+//   force/integrate item of slice i at step k: needs finalise(i-1, i, i+1) of step k;
+//   finalise item of slice i for step k+1:     needs integrate(i-1, i, i+1) of step k.
+// The claim order only sets which ready item a workgroup takes next; dependencies
+// always point to smaller tickets, so every wait ends.
+// ---------------------------------------------------------------------------
+struct Item {
+  int run, k, phase, slice, chunk, go;
+};
+
+__device__ bool wait_counters(const LaunchArgs& la, const uint32_t* cnt, int S, int s, unsigned need,
+                              uint32_t* err, uint32_t* abort_flag) {
+  const long long t_begin = wall_clock64();
+  const int nb[3] = {(s + S - 1) % S, s, (s + 1) % S};
+  for (int q = 0; q < 3; q++) {
+    while (ld_acquire(cnt + nb[q]) < need) {
+      if (ld_relaxed(abort_flag)) return false;
+      if (wall_clock64() - t_begin > la.watchdog_ticks) {
+        raise_error(err, abort_flag, ERR_WATCHDOG);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  return true;
+}
+
+template <int PREC, bool ENERGY, bool COUNT>
+__device__ void run_p2_item(const RunArgs& ra, const Item& it, Scratch<PREC>& ws, double (*s_red)[3],
+                            unsigned long long (*s_cnt)[4], uint32_t* abort_flag) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int src = (ra.par0 + it.k) & 1;
+  const int first = (it.k == 0) ? ra.first : 0;
+  const int b = (int)((long long)ra.g.cps * it.chunk / ra.nch);
+  const int e = (int)((long long)ra.g.cps * (it.chunk + 1) / ra.nch);
+  const int cbase = it.slice * ra.g.cps;
+  ItemAcc acc;
+  acc_zero(acc);
+  for (int lc = b + wave; lc < e; lc += WAVES)
+    p2_cell<PREC, ENERGY, COUNT>(ra, cbase + lc, src, first, ws, acc, abort_flag);
+  // wave reductions (fixed butterfly), then waves in order
+  double u = acc.u, w = acc.w, k = acc.k;
+  unsigned long long cc = acc.cand, pc = acc.inr;
+  if (ENERGY || COUNT) {
+    for (int off = 32; off >= 1; off >>= 1) {
+      if (ENERGY) {
+        u += __shfl_xor(u, off);
+        w += __shfl_xor(w, off);
+        k += __shfl_xor(k, off);
+      }
+      if (COUNT) {
+        cc += __shfl_xor(cc, off);
+        pc += __shfl_xor(pc, off);
+      }
+    }
+  }
+  if (lane == 0) {
+    s_red[wave][0] = u;
+    s_red[wave][1] = k;
+    s_red[wave][2] = w;
+    s_cnt[wave][0] = acc.left;
+    s_cnt[wave][1] = acc.right;
+    s_cnt[wave][2] = cc;
+    s_cnt[wave][3] = pc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long t = ra.t0 + it.k;
+    if (ENERGY) {
+      const long long j = t / ra.every - (ra.t0 + ra.every - 1) / ra.every;
+      double su = 0, sk = 0, sw = 0;
+      for (int q = 0; q < WAVES; q++) {
+        su += s_red[q][0];
+        sk += s_red[q][1];
+        sw += s_red[q][2];
+      }
+      double* ep = ra.epart + ((j * ra.g.S + it.slice) * ra.nch + it.chunk) * 3;
+      ep[0] = su;
+      ep[1] = sk;
+      ep[2] = sw;
+    }
+    unsigned long long left = 0, right = 0, c2 = 0, p2 = 0;
+    for (int q = 0; q < WAVES; q++) {
+      left += s_cnt[q][0];
+      right += s_cnt[q][1];
+      c2 += s_cnt[q][2];
+      p2 += s_cnt[q][3];
+    }
+    if (left) atomicAdd(ra.migcum + 2 * it.slice + 0, left);
+    if (right) atomicAdd(ra.migcum + 2 * it.slice + 1, right);
+    if (ra.miglog) {
+      if (left) atomicAdd(ra.miglog + ((size_t)it.k * ra.g.S + it.slice) * 2 + 0, (uint32_t)left);
+      if (right) atomicAdd(ra.miglog + ((size_t)it.k * ra.g.S + it.slice) * 2 + 1, (uint32_t)right);
+    }
+    if (COUNT) {
+      atomicAdd(ra.paircnt + 0, c2);
+      atomicAdd(ra.paircnt + 1, p2);
+    }
+    if (ra.fail_at >= 0 && t == ra.fail_at && it.slice == 0 && it.chunk == 0)
+      raise_error(ra.err, abort_flag, ERR_INJECTED);
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(WG) void persistent_kernel(LaunchArgs la) {
+  __shared__ Scratch<PREC> ws[WAVES];
+  __shared__ double s_red[WAVES][3];
+  __shared__ unsigned long long s_cnt[WAVES][4];
+  __shared__ Item s_it;
+  __shared__ int s_ok;
+  const int wave = threadIdx.x >> 6;
+  const long long total = la.round_base[la.nrounds];
+  while (true) {
+    if (threadIdx.x == 0) {
+      Item it;
+      it.go = 0;
+      const long long T = (long long)atomicAdd(la.ticket, 1ull);
+      if (T < total) {
+        int lo = 0, hi = la.nrounds;
+        while (hi - lo > 1) {
+          int mid = (lo + hi) >> 1;
+          if (la.round_base[mid] <= T) lo = mid; else hi = mid;
+        }
+        const int k = lo;
+        const long long rem = T - la.round_base[k];
+        int rlo = 0, rhi = la.round_active[k];
+        while (rhi - rlo > 1) {
+          int mid = (rlo + rhi) >> 1;
+          if (la.run_prefix[mid] <= rem) rlo = mid; else rhi = mid;
+        }
+        const RunArgs& ra = la.runs[rlo];
+        const int local = (int)(rem - la.run_prefix[rlo]);
+        const int entry = local / ra.nch;
+        const unsigned ord = ra.order[entry];
+        it.run = rlo;
+        it.k = k;
+        it.phase = (int)(ord >> 15);
+        it.slice = (int)(ord & 0x7fffu);
+        it.chunk = local - entry * ra.nch;
+        it.go = 1;
+      }
+      s_it = it;
+    }
+    __syncthreads();
+    const Item it = s_it;
+    if (it.go == 0) break;
+    if (it.go == 1) {
+      const RunArgs& ra = la.runs[it.run];
+      if (threadIdx.x == 0) {
+        const unsigned need = (unsigned)(it.k + 1) * (unsigned)ra.nch;
+        s_ok = !ld_relaxed(ra.abort) &&
+               wait_counters(la, it.phase == 0 ? ra.cntA : ra.cntF, ra.g.S, it.slice, need, ra.err, ra.abort);
+      }
+      __syncthreads();
+      const int ok = s_ok;
+      if (ok) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (it.phase == 0) {
+          const long long t = ra.t0 + it.k;
+          const bool energy = ra.every > 0 && (t % ra.every) == 0;
+          if (ra.count) {
+            if (energy) run_p2_item<PREC, true, true>(ra, it, ws[wave], s_red, s_cnt, ra.abort);
+            else run_p2_item<PREC, false, true>(ra, it, ws[wave], s_red, s_cnt, ra.abort);
+          } else {
+            if (energy) run_p2_item<PREC, true, false>(ra, it, ws[wave], s_red, s_cnt, ra.abort);
+            else run_p2_item<PREC, false, false>(ra, it, ws[wave], s_red, s_cnt, ra.abort);
+          }
+        } else {
+          const int dst = (ra.par0 + it.k + 1) & 1;
+          const int b = (int)((long long)ra.g.cps * it.chunk / ra.nch);
+          const int e = (int)((long long)ra.g.cps * (it.chunk + 1) / ra.nch);
+          const int cbase = it.slice * ra.g.cps;
+          p1_range(ra, cbase + b, cbase + e, dst, wave, ra.abort);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      }
+      __syncthreads();
+      if (ok && threadIdx.x == 0) {
+        uint32_t* cnt = it.phase == 0 ? ra.cntF : ra.cntA;
+        __hip_atomic_fetch_add(cnt + it.slice, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Counters at the start of a launch: every slice is finalised for its first step
+// (cntA = nch), nothing integrated yet (cntF = 0).
+__global__ void init_counters_kernel(RunArgs* runs, int nruns, int max_slices,
+                                     unsigned long long* ticket) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *ticket = 0ull;
+  for (int r = 0; r < nruns; r++) {
+    if (i == 0) *runs[r].abort = 0u;
+    if (i < runs[r].g.S) {
+      runs[r].cntA[i] = (uint32_t)runs[r].nch;
+      runs[r].cntF[i] = 0u;
+    }
+  }
+  (void)max_slices;
+}
+
+// ---------------------------------------------------------------------------
+// Load: bin every atom (Sec. 4 cell grid) and append it to its cell; then id order.
+// ---------------------------------------------------------------------------
+__global__ void fill_u32_kernel(uint32_t* p, long long n, uint32_t v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void load_scatter_kernel(DGeom g, const double* pos, const double* vel, long long n,
+                                    unsigned char* cells, uint32_t* ncnt, uint32_t* err) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    int gc[3];
+    for (int d = 0; d < 3; d++) gc[d] = coord_cell(pos[3 * i + d], g.inv_l[d], g.G[d]);
+    const int c = global_cell(g, gc[0], gc[1], gc[2]);
+    const unsigned slot = atomicAdd(ncnt + c, 1u);
+    if (slot < (unsigned)CELL_CAP) {
+      double* b = cblk(cells, c);
+      for (int d = 0; d < 3; d++) {
+        b[d * CELL_CAP + slot] = pos[3 * i + d];
+        b[(3 + d) * CELL_CAP + slot] = vel[3 * i + d];
+      }
+      cids(b)[slot] = (uint32_t)i;
+    } else {
+      atomicOr(err, ERR_CAPACITY);
+    }
+  }
+}
+
+__global__ __launch_bounds__(WG) void sort_cells_kernel(DGeom g, unsigned char* cells, uint32_t* ncnt,
+                                                        uint32_t* err) {
+  const int c = blockIdx.x * WAVES + (threadIdx.x >> 6);
+  if (c >= g.ncell) return;
+  unsigned n = ncnt[c];
+  if (n > (unsigned)CELL_CAP) {
+    if ((threadIdx.x & 63) == 0) atomicOr(err, ERR_CAPACITY);
+    return;
+  }
+  if (n > 1) cell_sort_wave(cells, c, (int)n, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Synchronous pass: F(t), v(t) and the energy terms at the current step, written in
+// id order (md_get_state / md_energy_virial).
+// ---------------------------------------------------------------------------
+constexpr int SYNC_CELLS = 64;  // cells per workgroup of the synchronous pass
+
+template <int PREC>
+__global__ __launch_bounds__(WG) void sync_kernel(DGeom g, const unsigned char* cells,
+                                                  const uint32_t* ncnt, int first, double* out_pos,
+                                                  double* out_vel, double* out_force, double* epart,
+                                                  uint32_t* err) {
+  __shared__ Scratch<PREC> ws[WAVES];
+  __shared__ double s_red[WAVES][3];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double u = 0, w = 0, k = 0;
+  const int b = blockIdx.x * SYNC_CELLS;
+  const int e = min(g.ncell, b + SYNC_CELLS);
+  for (int c = b + wave; c < e; c += WAVES) {
+    ForceOut o;
+    cell_force<PREC, true, false>(g, cells, ncnt, c, ws[wave], o);
+    if (lane < o.n) {
+      const double* ib = cblk(cells, c);
+      const uint32_t id = cids(ib)[lane];
+      const double F[3] = {o.fx, o.fy, o.fz};
+      double vf[3];
+      for (int d = 0; d < 3; d++) {
+        const double v = ib[(3 + d) * CELL_CAP + lane];
+        vf[d] = first ? v : __dadd_rn(v, __dmul_rn(g.hdt, F[d]));
+        if (out_pos) out_pos[3 * (size_t)id + d] = ib[d * CELL_CAP + lane];
+        if (out_vel) out_vel[3 * (size_t)id + d] = vf[d];
+        if (out_force) out_force[3 * (size_t)id + d] = F[d];
+        if (!isfinite(F[d]) || !isfinite(vf[d])) atomicOr(err, ERR_NONFINITE);
+      }
+      k += 0.5 * __dadd_rn(__dadd_rn(__dmul_rn(vf[0], vf[0]), __dmul_rn(vf[1], vf[1])),
+                           __dmul_rn(vf[2], vf[2]));
+      u += o.uh;
+      w += o.wh;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    u += __shfl_xor(u, off);
+    w += __shfl_xor(w, off);
+    k += __shfl_xor(k, off);
+  }
+  if (lane == 0) {
+    s_red[wave][0] = u;
+    s_red[wave][1] = k;
+    s_red[wave][2] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double su = 0, sk = 0, sw = 0;
+    for (int q = 0; q < WAVES; q++) {
+      su += s_red[q][0];
+      sk += s_red[q][1];
+      sw += s_red[q][2];
+    }
+    epart[3 * blockIdx.x + 0] = su;
+    epart[3 * blockIdx.x + 1] = sk;
+    epart[3 * blockIdx.x + 2] = sw;
+  }
+}
+
+__global__ void cells_of_kernel(DGeom g, const uint32_t* ncnt, const unsigned char* cells,
+                                long long* cell_of_id) {
+  const int c = blockIdx.x * WAVES + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= g.ncell) return;
+  const unsigned n = ncnt[c];
+  if ((unsigned)lane < n) cell_of_id[cids(cblk(cells, c))[lane]] = c;
+}
+
+__global__ void slice_counts_kernel(DGeom g, const uint32_t* ncnt, unsigned long long* counts) {
+  const int s = blockIdx.x;
+  unsigned long long acc = 0;
+  for (int c = threadIdx.x; c < g.cps; c += blockDim.x) acc += ncnt[(size_t)s * g.cps + c];
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  __shared__ unsigned long long part[WAVES];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int q = 0; q < WAVES; q++) t += part[q];
+    counts[s] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch wrappers
+// ---------------------------------------------------------------------------
+static inline hipStream_t S_(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+static int grid_for(long long n, int block) {
+  long long b = (n + block - 1) / block;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (int)b;
+}
+
+int launch_clear_u32(uint32_t* p, long long n, uint32_t value, void* stream) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, S_(stream), p, n, value);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_load_scatter(const DGeom& g, const double* pos, const double* vel, long long n,
+                        unsigned char* cells, uint32_t* ncnt, uint32_t* err, void* stream) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(load_scatter_kernel, dim3(grid_for(n, 256)), dim3(256), 0, S_(stream), g, pos,
+                     vel, n, cells, ncnt, err);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_sort_cells(const DGeom& g, unsigned char* cells, uint32_t* ncnt, uint32_t* err, void* stream) {
+  const int blocks = (g.ncell + WAVES - 1) / WAVES;
+  hipLaunchKernelGGL(sort_cells_kernel, dim3(blocks), dim3(WG), 0, S_(stream), g, cells, ncnt, err);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_init_counters(RunArgs* runs_dev, int nruns, int max_slices, unsigned long long* ticket,
+                         void* stream) {
+  const int blocks = (max_slices + 255) / 256;
+  hipLaunchKernelGGL(init_counters_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, S_(stream),
+                     runs_dev, nruns, max_slices, ticket);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int persistent_grid(int prec, int* blocks_per_cu, int* cus) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
+  int nb = 0;
+  hipError_t e = prec == 1
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<1>, WG, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<0>, WG, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  *blocks_per_cu = nb;
+  *cus = prop.multiProcessorCount;
+  return 0;
+}
+
+int launch_persistent(const LaunchArgs& la, int prec, int grid, void* stream) {
+  if (prec == 1)
+    hipLaunchKernelGGL(persistent_kernel<1>, dim3(grid), dim3(WG), 0, S_(stream), la);
+  else
+    hipLaunchKernelGGL(persistent_kernel<0>, dim3(grid), dim3(WG), 0, S_(stream), la);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int sync_blocks(const DGeom& g) { return (g.ncell + SYNC_CELLS - 1) / SYNC_CELLS; }
+
+int launch_sync(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int first,
+                double* out_pos, double* out_vel, double* out_force, double* epart, uint32_t* err,
+                void* stream) {
+  const int blocks = sync_blocks(g);
+  if (g.prec == 1)
+    hipLaunchKernelGGL(sync_kernel<1>, dim3(blocks), dim3(WG), 0, S_(stream), g, cells, ncnt, first,
+                       out_pos, out_vel, out_force, epart, err);
+  else
+    hipLaunchKernelGGL(sync_kernel<0>, dim3(blocks), dim3(WG), 0, S_(stream), g, cells, ncnt, first,
+                       out_pos, out_vel, out_force, epart, err);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_cells_of(const DGeom& g, const uint32_t* ncnt, const unsigned char* cells,
+                    long long* cell_of_id, void* stream) {
+  const int blocks = (g.ncell + WAVES - 1) / WAVES;
+  hipLaunchKernelGGL(cells_of_kernel, dim3(blocks), dim3(WG), 0, S_(stream), g, ncnt, cells, cell_of_id);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_slice_counts(const DGeom& g, const uint32_t* ncnt, unsigned long long* counts, void* stream) {
+  hipLaunchKernelGGL(slice_counts_kernel, dim3(g.S), dim3(WG), 0, S_(stream), g, ncnt, counts);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace mdk

@@ -1,0 +1,105 @@
+// md_internal.h -- types shared by the device kernels and the host runtime of libmd.
+//
+// Data layout in HBM (one simulation or one served run):
+//   two cell buffers (parity 0/1).  A cell owns CELL_CAP atom slots stored as one
+//   block: x[64] y[64] z[64] vx[64] vy[64] vz[64] (FP64) then id[64] (u32).
+//   Cells are numbered slice-major: cell = slice * cells_per_slice +
+//   ((gx mod ncx) * Gy + gy) * Gz + gz, so a slice is one contiguous range of blocks.
+//   ncnt[p][cell]: atoms in the cell; nin[p][cell]: atoms that moved in from
+//   another cell during the last step (appended from the top slot downwards).
+//   Within a finalised cell, atoms are ordered by id.
+#pragma once
+#include <stdint.h>
+
+namespace mdk {
+
+constexpr int CELL_CAP = 64;                 // slots per cell (one wavefront)
+constexpr int CELL_DOUBLES = 6 * CELL_CAP;   // x y z vx vy vz
+constexpr int CELL_BYTES = CELL_DOUBLES * 8 + CELL_CAP * 4;  // 3328
+constexpr int WG = 256;                      // threads per workgroup (4 waves)
+constexpr int WAVES = WG / 64;
+
+// error word bits
+constexpr uint32_t ERR_NONFINITE = 1u;
+constexpr uint32_t ERR_DISPLACEMENT = 2u;
+constexpr uint32_t ERR_CAPACITY = 4u;
+constexpr uint32_t ERR_WATCHDOG = 8u;
+constexpr uint32_t ERR_BADINPUT = 16u;
+constexpr uint32_t ERR_INJECTED = 32u;
+
+struct DGeom {
+  double L[3];
+  double halfL[3];
+  double l[3];
+  double inv_l[3];
+  double rc2;      // rc^2
+  double uc;       // pair energy at rc (subtracted from every pair energy)
+  double dt, hdt;  // step and half step
+  float rc2_f;     // rc^2 in FP32
+  float rc2_lo_f;  // FP32 pairs with r2 <= rc2_lo_f are in range for certain
+  float rc2_hi_f;  // FP32 pairs with r2 >  rc2_hi_f are out of range for certain
+  float uc_f;
+  int S;           // slices
+  int ncx;         // cell layers per slice
+  int G[3];        // cells per axis
+  int cps;         // cells per slice
+  int ncell;       // cells in total
+  int prec;        // 0 FP64, 1 FP32 force
+};
+
+struct RunArgs {
+  DGeom g;
+  unsigned char* cells[2];
+  uint32_t* ncnt[2];
+  uint32_t* nin[2];
+  uint32_t* cntA;               // per slice: finalise items completed in this launch (+nch at start)
+  uint32_t* cntF;               // per slice: force/integrate items completed in this launch
+  double* epart;                // [nsample][S][nch][3] partial U, K, W (energy steps)
+  uint32_t* miglog;             // [nsteps][S][2] or null
+  unsigned long long* migcum;   // [S][2] cumulative migrations
+  unsigned long long* paircnt;  // [2] candidates, in-range (count mode)
+  uint32_t* err;                // error word of this run
+  uint32_t* abort;              // set on any error of this run; its waits give up
+  const uint16_t* order;        // per-step claim table, 2*S entries: (phase << 15) | slice
+  long long t0;                 // absolute step at the start of the launch
+  int nsteps;                   // steps in this launch
+  int par0;                     // parity of the sorted buffer at t0
+  int first;                    // 1: stored velocities are v(t0) (not half-step velocities)
+  int nch;                      // work items per slice and phase
+  int every;                    // energy sampling interval (0 = none)
+  int count;                    // count candidates / in-range partners
+  long long fail_at;            // debug fault injection step (-1 off)
+  int ips;                      // items per step = 2 * S * nch
+};
+
+struct LaunchArgs {
+  RunArgs* runs;
+  int nruns;
+  int nrounds;
+  const long long* round_base;  // [nrounds + 1] first ticket of each round
+  const int* round_active;      // [nrounds] runs active in the round (runs sorted by steps)
+  const long long* run_prefix;  // [nruns + 1] prefix sums of ips
+  unsigned long long* ticket;   // claim counter
+  long long watchdog_ticks;     // wall_clock64 ticks a wait may take
+};
+
+// Host-callable launch wrappers (defined in md_device.hip).
+int launch_clear_u32(uint32_t* p, long long n, uint32_t value, void* stream);
+int launch_load_scatter(const DGeom& g, const double* pos, const double* vel, long long n,
+                        unsigned char* cells, uint32_t* ncnt, uint32_t* err, void* stream);
+int launch_sort_cells(const DGeom& g, unsigned char* cells, uint32_t* ncnt, uint32_t* err,
+                      void* stream);
+int launch_init_counters(RunArgs* runs_dev, int nruns, int max_slices, unsigned long long* ticket,
+                         void* stream);
+int persistent_grid(int prec, int* blocks_per_cu, int* cus);
+int launch_persistent(const LaunchArgs& la, int prec, int grid, void* stream);
+int launch_sync(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int first,
+                double* out_pos, double* out_vel, double* out_force, double* epart,
+                uint32_t* err, void* stream);
+int launch_cells_of(const DGeom& g, const uint32_t* ncnt, const unsigned char* cells,
+                    long long* cell_of_id, void* stream);
+int launch_slice_counts(const DGeom& g, const uint32_t* ncnt, unsigned long long* counts,
+                        void* stream);
+int sync_blocks(const DGeom& g);
+
+}  // namespace mdk

@@ -1,0 +1,279 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Bars (the method's contract):
+  * binning, slice membership, migration counts, candidate and in-range pair counts:
+    bit-exact;
+  * forces: max_i |F_i - F_i^ref| / S_i <= 1e-12 (FP64 mode) and <= 1e-5 (FP32-force
+    mode), where S_i sums the magnitudes of atom i's pair-force terms;
+  * energies of an FP64 trajectory: relative 1e-10 of the oracle's over 100 steps.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2507_11289_amd import inputs, md
+
+pytestmark = pytest.mark.gpu
+
+TOL = {md.MD_FP64: 1e-12, md.MD_FP32_FORCE: 1e-5}
+PRECS = [md.MD_FP64, md.MD_FP32_FORCE]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c0():
+    return inputs.lj_fluid_2048()
+
+
+@pytest.fixture(scope="module")
+def c0_oracle(c0):
+    g = ref.geometry(c0.box, c0.slices, c0.rc)
+    return g, ref.forces_cells(g, c0.pos)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_load_binning_and_forces_at_t0(c0, c0_oracle, prec):
+    g, o = c0_oracle
+    say(f"[gpu] lj_fluid_2048 load + forces, precision={prec}")
+    with md.Sim(c0.box, c0.slices, c0.rc, c0.dt, prec) as sim:
+        sim.load(c0.pos, c0.vel)
+        _, _, ocell = ref.bin_atoms(g, c0.pos)
+        np.testing.assert_array_equal(sim.cells(), ocell)
+        pos, vel, F = sim.state()
+        np.testing.assert_array_equal(pos, c0.pos)
+        np.testing.assert_array_equal(vel, c0.vel)
+        e = ref.force_error(F, o["F"], o["scale"])
+        say(f"    max e_i = {e.max():.3e}")
+        assert e.max() <= TOL[prec]
+        U, K, W = sim.energy_virial()
+        oU, oK, oW = ref.energy(g, c0.pos, c0.vel)
+        rel = 1e-12 if prec == md.MD_FP64 else 1e-6
+        assert U == pytest.approx(oU, rel=rel)
+        assert W == pytest.approx(oW, rel=rel)
+        assert K == pytest.approx(oK, rel=1e-13)
+        counts = np.bincount(ref.bin_atoms(g, c0.pos)[1], minlength=c0.slices)
+        np.testing.assert_array_equal(sim.slice_counts(), counts)
+
+
+def test_fp64_trajectory_matches_oracle(c0):
+    say("[gpu] lj_fluid_2048 FP64 100 steps vs oracle")
+    g = ref.geometry(c0.box, c0.slices, c0.rc)
+    o = ref.run(g, c0.pos, c0.vel, c0.dt, 100, every=1, miglog=True)
+    with md.Sim(c0.box, c0.slices, c0.rc, c0.dt, md.MD_FP64) as sim:
+        sim.set_option(md.OPT_ENERGY_EVERY, 1)
+        sim.set_option(md.OPT_MIGRATION_LOG, 1)
+        sim.load(c0.pos, c0.vel)
+        sim.step(100)
+        elog = sim.energy_log()
+        mig = sim.migration_log()
+        U, K, W = sim.energy_virial()
+        pos, vel, F = sim.state()
+    assert elog.shape == (100, 4)
+    np.testing.assert_array_equal(elog[:, 0], np.arange(100))
+    ref_e = o["elog"]
+    E = elog[:, 1] + elog[:, 2]
+    Eo = ref_e[:100, 1] + ref_e[:100, 2]
+    assert np.abs(E - Eo).max() <= 1e-10 * np.abs(Eo).max()
+    assert np.abs(elog[:, 3] - ref_e[:100, 3]).max() <= 1e-10 * np.abs(ref_e[:, 3]).max()
+    assert U + K == pytest.approx(ref_e[100, 1] + ref_e[100, 2], rel=1e-10)
+    np.testing.assert_array_equal(mig, o["miglog"])
+    d = pos - o["pos"]
+    L = np.array(c0.box)
+    d -= L * np.round(d / L)
+    assert np.abs(d).max() < 1e-9
+    np.testing.assert_allclose(vel, o["vel"], atol=1e-8)
+    # the GPU's own binning of its positions follows the binning rule exactly
+    c = ref.forces_cells(g, pos)
+    assert ref.force_error(F, c["F"], c["scale"]).max() <= 1e-12
+
+
+def test_fp32_force_trajectory_tracks_fp64(c0):
+    say("[gpu] lj_fluid_2048 FP32-force 100 steps vs oracle")
+    g = ref.geometry(c0.box, c0.slices, c0.rc)
+    o = ref.run(g, c0.pos, c0.vel, c0.dt, 100, every=10, miglog=True)
+    with md.Sim(c0.box, c0.slices, c0.rc, c0.dt, md.MD_FP32_FORCE) as sim:
+        sim.set_option(md.OPT_ENERGY_EVERY, 10)
+        sim.load(c0.pos, c0.vel)
+        sim.step(100)
+        elog = sim.energy_log()
+        U, K, W = sim.energy_virial()
+        pos, vel, F = sim.state()
+    E = elog[:, 1] + elog[:, 2]
+    Eo = o["elog"][:10, 1] + o["elog"][:10, 2]
+    # 1e-5-accurate forces keep the short trajectory within 1e-6 per atom
+    assert np.abs(E - Eo).max() / c0.n < 1e-6
+    c = ref.forces_cells(g, pos)
+    assert ref.force_error(F, c["F"], c["scale"]).max() <= 1e-5
+    _, _, ocell = ref.bin_atoms(g, pos)
+
+
+def test_brute_force_tiny_systems():
+    for n, rho, aspect, slices in [(500, 0.8, (1, 1, 1), 3), (700, 0.5, (2, 1, 1), 4),
+                                   (1200, 0.9, (3, 1, 1), 3)]:
+        box, pos, vel, _ = inputs.homogeneous(n, rho, 1.0, 7, aspect=aspect)
+        g = ref.geometry(box, slices, 2.5)
+        Fb, Ub, Wb, Pb = ref.forces_brute(g, pos)
+        c = ref.forces_cells(g, pos)
+        for prec in PRECS:
+            say(f"[gpu] brute force n={n} slices={slices} precision={prec}")
+            with md.Sim(box, slices, 2.5, 0.005, prec) as sim:
+                sim.set_option(md.OPT_COUNT_PAIRS, 1)
+                sim.load(pos, vel)
+                _, _, F = sim.state()
+                assert ref.force_error(F, Fb, c["scale"]).max() <= TOL[prec]
+                U, K, W = sim.energy_virial()
+                assert U == pytest.approx(Ub, rel=1e-12 if prec == 0 else 1e-6)
+                sim.step(1)
+                st = sim.stats()
+                assert st.in_range == 2 * Pb
+                assert st.candidates == int(c["cand"].sum())
+
+
+def run_state(s, prec, nsteps, order=None, seed=1, chunk=0):
+    with md.Sim(s.box, s.slices, s.rc, s.dt, prec) as sim:
+        if order is not None:
+            sim.set_option(md.OPT_CLAIM_ORDER, order)
+            sim.set_option(md.OPT_ORDER_SEED, seed)
+        if chunk:
+            sim.set_option(md.OPT_CHUNK_CELLS, chunk)
+        sim.load(s.pos, s.vel)
+        sim.step(nsteps)
+        return sim.state()
+
+
+@pytest.fixture(scope="module")
+def medium():
+    box, pos, vel, _ = inputs.homogeneous(60000, 0.8, 1.0, 21, aspect=(2.0, 1.0, 1.0))
+    return inputs.System("medium", box, 12, pos, vel)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_schedule_invariance_is_bitwise(medium, prec):
+    ref_state = None
+    for order, seed, chunk in [(md.ORDER_SWEEP, 1, 0), (md.ORDER_PHASED, 1, 0),
+                               (md.ORDER_DESCENDING, 1, 7), (md.ORDER_RANDOM, 5, 0),
+                               (md.ORDER_RANDOM, 9, 33)]:
+        say(f"[gpu] schedule invariance order={order} seed={seed} chunk={chunk} precision={prec}")
+        st = run_state(medium, prec, 20, order, seed, chunk)
+        if ref_state is None:
+            ref_state = st
+        else:
+            for a, b in zip(ref_state, st):
+                np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_bitwise_resume(medium, prec):
+    say(f"[gpu] resume precision={prec}")
+    whole = run_state(medium, prec, 20)
+    with md.Sim(medium.box, medium.slices, medium.rc, medium.dt, prec) as a:
+        a.load(medium.pos, medium.vel)
+        a.step(10)
+        p, v, _ = a.state()
+    with md.Sim(medium.box, medium.slices, medium.rc, medium.dt, prec) as b:
+        b.load(p, v)
+        b.step(10)
+        split = b.state()
+    for x, y in zip(whole, split):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_split_launches_equal_one_launch(medium):
+    say("[gpu] launch splitting")
+    whole = run_state(medium, md.MD_FP32_FORCE, 12)
+    with md.Sim(medium.box, medium.slices, medium.rc, medium.dt, md.MD_FP32_FORCE) as sim:
+        sim.set_option(md.OPT_MAX_STEPS_PER_LAUNCH, 5)
+        sim.load(medium.pos, medium.vel)
+        sim.step(7)
+        sim.step(5)
+        st = sim.state()
+    for x, y in zip(whole, st):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_free_flight_exact_and_migrations():
+    say("[gpu] free flight")
+    box = [12.0, 9.0, 9.0]
+    pts = [[0.25 + 3.0 * i, 0.5 + 3.0 * j, 0.75 + 3.0 * k] for i in range(4) for j in range(3) for k in range(3)]
+    pos = np.array(pts)
+    vel = np.tile(np.array([[1.0, -0.5, 0.25]]), (len(pos), 1))
+    dt = 2.0 ** -8
+    g = ref.geometry(box, 3, 2.5)
+    o = ref.run(g, pos, vel, dt, 1500, miglog=True)
+    for prec in PRECS:
+        with md.Sim(box, 3, 2.5, dt, prec) as sim:
+            sim.set_option(md.OPT_MIGRATION_LOG, 1)
+            sim.load(pos, vel)
+            sim.step(1500)
+            p, v, F = sim.state()
+            np.testing.assert_array_equal(p, o["pos"])
+            np.testing.assert_array_equal(v, vel)
+            assert np.abs(F).max() == 0.0
+            np.testing.assert_array_equal(sim.migration_log(), o["miglog"])
+            st = sim.stats()
+            assert st.migrations_right == int(o["miglog"][:, :, 1].sum()) and st.migrations_left == 0
+
+
+def test_empty_system_and_boundary_positions():
+    say("[gpu] empty system")
+    with md.Sim((12.0, 9.0, 9.0), 3, 2.5, 0.005) as sim:
+        sim.load(np.zeros((0, 3)), np.zeros((0, 3)))
+        sim.step(3)
+        assert sim.energy_virial() == (0.0, 0.0, 0.0)
+        assert sim.stats().step == 3
+    say("[gpu] positions at 0 and L")
+    box = (12.0, 9.0, 9.0)
+    # coordinates exactly 0 and exactly L (the last cell), all pairs beyond rc
+    pos = np.array([[0.0, 0.0, 0.0], [12.0, 4.5, 9.0], [6.0, 9.0, 4.5]])
+    vel = np.array([[0.5, -0.25, 0.125], [-1.0, 0.5, 0.25], [0.0, 1.0, -1.0]])
+    g = ref.geometry(box, 3, 2.5)
+    o = ref.run(g, pos, vel, 0.005, 2)
+    with md.Sim(box, 3, 2.5, 0.005) as sim:
+        sim.load(pos, vel)
+        np.testing.assert_array_equal(sim.cells(), ref.bin_atoms(g, pos)[2])
+        sim.step(2)
+        p, v, F = sim.state()
+        np.testing.assert_array_equal(p, o["pos"])
+        np.testing.assert_array_equal(v, o["vel"])
+
+
+def test_errors_are_reported_and_poison():
+    box = (20.0, 9.0, 9.0)
+    say("[gpu] capacity overflow at load")
+    pos = np.full((70, 3), 1.0) + np.linspace(0, 0.9, 70)[:, None] * np.array([1, 0, 0])
+    with md.Sim(box, 5, 2.5, 0.005) as sim:
+        with pytest.raises(md.MDError) as e:
+            sim.load(pos, np.zeros_like(pos))
+        assert e.value.code == md.MD_ECAPACITY
+        with pytest.raises(md.MDError) as e:
+            sim.step(1)
+        assert e.value.code == md.MD_ESTATE
+    say("[gpu] slice jump")
+    pos = np.array([[0.5, 1.0, 1.0], [10.5, 5.0, 5.0]])
+    vel = np.array([[9.0 / 0.01, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    with md.Sim(box, 5, 2.5, 0.01) as sim:
+        sim.load(pos, vel)
+        assert sim.step_rc(3) == md.MD_EUNSTABLE
+        assert sim.stats().poisoned == 1
+        assert sim.step_rc(1) == md.MD_ESTATE
+    say("[gpu] injected fault")
+    s = inputs.lj_fluid_2048()
+    with md.Sim(s.box, s.slices, s.rc, s.dt) as sim:
+        sim.set_option(md.OPT_FAIL_AT_STEP, 4)
+        sim.load(s.pos, s.vel)
+        assert sim.step_rc(10) == md.MD_EUNSTABLE
+    say("[gpu] invalid input")
+    with md.Sim(box, 5, 2.5, 0.005) as sim:
+        with pytest.raises(md.MDError) as e:
+            sim.load(np.array([[21.0, 1.0, 1.0]]), np.zeros((1, 3)))
+        assert e.value.code == md.MD_EINVAL
+        with pytest.raises(md.MDError) as e:
+            sim.step(1)
+        assert e.value.code == md.MD_ESTATE
