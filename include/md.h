@@ -62,7 +62,8 @@ enum md_precision {
 /* md_set_option keys */
 enum md_option {
     MD_OPT_ENERGY_EVERY = 1,    /* sample U, K, W at steps t with t % k == 0 (0 = never); default 0 */
-    MD_OPT_CLAIM_ORDER = 2,     /* md_claim_order; results are identical for every order */
+    MD_OPT_CLAIM_ORDER = 2,     /* md_claim_order (default MD_ORDER_DATAFLOW); results are
+                                   bitwise identical for every order */
     MD_OPT_ORDER_SEED = 3,      /* seed of MD_ORDER_RANDOM */
     MD_OPT_MIGRATION_LOG = 4,   /* 1: record per-step, per-slice migration counts */
     MD_OPT_CHUNK_CELLS = 5,     /* cells per work item (0 = automatic) */
@@ -70,7 +71,8 @@ enum md_option {
     MD_OPT_WATCHDOG_MS = 7,     /* device wait budget in ms (default 20000) */
     MD_OPT_GRID = 8,            /* persistent workgroups (0 = occupancy x CUs) */
     MD_OPT_FAIL_AT_STEP = 9,    /* debug: raise MD_EUNSTABLE when step k is reached (-1 = off) */
-    MD_OPT_MAX_STEPS_PER_LAUNCH = 10 /* split md_step into launches of at most k steps */
+    MD_OPT_MAX_STEPS_PER_LAUNCH = 10, /* split md_step into launches of at most k steps */
+    MD_OPT_TRACE = 11           /* 1: record one md_trace_rec per work item of the next md_step */
 };
 
 enum md_claim_order {
@@ -78,7 +80,9 @@ enum md_claim_order {
                                  its neighbours are integrated (the stage order of Table 1) */
     MD_ORDER_PHASED = 1,      /* all force/integrate items of a step, then all finalise items */
     MD_ORDER_DESCENDING = 2,  /* the sweep mirrored */
-    MD_ORDER_RANDOM = 3       /* a seeded random order that respects the dependencies */
+    MD_ORDER_RANDOM = 3,      /* a seeded random order that respects the dependencies */
+    MD_ORDER_DATAFLOW = 4     /* items are queued the moment their inputs are complete and
+                                 taken in queue order (no worker waits on a dependency) */
 };
 
 typedef struct md_stats {
@@ -149,6 +153,19 @@ int md_get_energy_log(md_sim *s, int64_t cap_rows, double *rows, int64_t *count)
 /* Migration log of the last md_step (MD_OPT_MIGRATION_LOG): [steps][S][2] counts of
  * atoms leaving slice s to the left (0) and to the right (1) in each step. */
 int md_get_migration_log(md_sim *s, int64_t cap_steps, int32_t *log, int64_t *steps);
+
+/* One work item of a persistent launch (MD_OPT_TRACE): which item, on which compute
+ * unit, and when (device wall clock ticks) it was claimed, found its inputs ready,
+ * and finished.  phase 0 = force/integrate of step k, 1 = finalise of step k+1. */
+typedef struct md_trace_rec {
+    uint32_t k, slice, chunk, phase;
+    uint32_t hw_id;            /* hardware id register of the wave that ran it */
+    uint32_t launch;           /* index of the persistent launch within md_step */
+    uint64_t t_claim, t_ready, t_done;
+} md_trace_rec;
+
+/* Trace of the last md_step; *count = records available; ticks per second in *hz. */
+int md_get_trace(md_sim *s, int64_t cap, md_trace_rec *out, int64_t *count, double *hz);
 
 int md_get_stats(md_sim *s, md_stats *out);
 int md_set_option(md_sim *s, int key, int64_t value);

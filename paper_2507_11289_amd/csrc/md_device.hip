@@ -11,20 +11,23 @@
 //     energy/virial collection (stat_collect); new positions and the runtime decision
 //     in which slice a molecule is stored (md_v3b).
 //   * Sec. 3.1-3.3 / Table 1: a slice is processed once its neighbours are present; on
-//     one GPU this becomes a persistent kernel whose work items wait on per-slice
+//     one GPU this becomes a persistent kernel whose work items follow per-slice
 //     counters (slice i advances t -> t+1 once i-1 and i+1 reached t).
 //
 // One wavefront owns one cell at a time.  A cell's atoms sit in slots 0..n-1 of its
-// 64-slot block, ordered by id, so the force sum of every atom has a fixed order and
-// the whole trajectory is bitwise independent of the claim order of the work items.
+// 64-slot block, ordered by id, so every atom's force sum has a fixed order and the
+// trajectory is bitwise independent of the order in which work items run.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "md_internal.h"
 
 namespace mdk {
 
-constexpr int TILE = 256;  // neighbour candidates staged in LDS per pass
+constexpr int TILE = 256;                 // candidates staged in LDS per pass
+constexpr int MAXCAND = 27 * CELL_CAP;    // candidates of one cell at most
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -97,28 +100,36 @@ __device__ __forceinline__ double wrap1(double x, double L) {
   return x >= L ? __dsub_rn(x, L) : (x < 0.0 ? __dadd_rn(x, L) : x);
 }
 
+// 1/x in FP64 from the hardware reciprocal and two Newton steps (within one ulp).
+__device__ __forceinline__ double recip64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
 // ---------------------------------------------------------------------------
 // per-wave LDS scratch
 // ---------------------------------------------------------------------------
+struct ScratchBase {
+  int nb_cell[28];            // global cell of neighbour m = (ox+1)*9 + (oy+1)*3 + (oz+1)
+  uint16_t tag[MAXCAND];      // flat candidate index -> (m << 6) | slot
+};
 template <int PREC> struct Scratch;
-template <> struct Scratch<1> {  // FP32 pair math: cell-relative FP32 positions + tag
-  int nb_cell[28];
-  int nb_pre[28];
+template <> struct Scratch<1> : ScratchBase {  // FP32 pair math on cell-relative positions
   union {
     float4 q[TILE];
     double red[64 * 6];
   };
 };
-template <> struct Scratch<0> {  // FP64 pair math: raw FP64 positions + tag
-  int nb_cell[28];
-  int nb_pre[28];
+template <> struct Scratch<0> : ScratchBase {  // FP64 pair math on raw positions
   union {
     struct {
       double x[TILE], y[TILE], z[TILE];
     } t;
     double red[64 * 6];
   };
-  uint32_t tag[TILE];
 };
 
 struct ForceOut {
@@ -129,28 +140,104 @@ struct ForceOut {
   int total;          // candidates in the 27 cells, self included (uniform)
 };
 
-// Candidate (m, k): neighbour m in 0..26, slot k.  m = (ox+1)*9 + (oy+1)*3 + (oz+1).
-__device__ __forceinline__ unsigned make_tag(int m, int k) { return ((unsigned)m << 6) | (unsigned)k; }
+// Partial sums of one i-atom held by one lane.
+template <class R> struct Acc {
+  R fx, fy, fz;
+  double u, w;
+  unsigned pc;
+  bool band;  // a pair fell in the FP32 guard band and still has to be decided exactly
+};
 
-// Exact FP64 in-range decision for a pair whose FP32 r^2 fell in the guard band.
-__device__ __noinline__ bool exact_in_range(const DGeom& g, double xi, double yi, double zi,
-                                            const unsigned char* cells, int nc, int k) {
-  const double* jb = cblk(cells, nc);
-  double dx = min_img(__dsub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
-  double dy = min_img(__dsub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
-  double dz = min_img(__dsub_rn(zi, jb[2 * CELL_CAP + k]), g.L[2], g.halfL[2]);
-  return r2_exact(dx, dy, dz) <= g.rc2;
+template <class R> __device__ __forceinline__ void acc_init(Acc<R>& a) {
+  a.fx = a.fy = a.fz = (R)0;
+  a.u = a.w = 0.0;
+  a.pc = 0;
+  a.band = false;
+}
+
+// FP32 pair for one i-atom against one staged candidate (Algorithm 1 loop body).
+// In range for certain when 0 < r2 <= rc2_lo (r2 == 0 only for the atom itself);
+// pairs with rc2_lo < r2 <= rc2_hi are marked and decided again in FP64 later.
+template <bool ENERGY, bool COUNT>
+__device__ __forceinline__ void pair32(float qx, float qy, float qz, const float4& q, unsigned lo_bits,
+                                       unsigned hi_bits, float ucf, Acc<float>& a) {
+  const float dx = qx - q.x, dy = qy - q.y, dz = qz - q.z;
+  const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  const unsigned rb = __float_as_uint(r2) - 1u;
+  const bool in = rb < lo_bits;
+  a.band |= (rb < hi_bits) & !in;
+  const float ir2 = __builtin_amdgcn_rcpf(r2);
+  const float ir6 = ir2 * ir2 * ir2;
+  const float t = fmaf(2.0f, ir6, -1.0f);
+  float fr = 24.0f * ir2 * ir6 * t;
+  fr = in ? fr : 0.0f;
+  a.fx = fmaf(fr, dx, a.fx);
+  a.fy = fmaf(fr, dy, a.fy);
+  a.fz = fmaf(fr, dz, a.fz);
+  if (ENERGY) {
+    a.u += in ? (double)(4.0f * ir6 * (ir6 - 1.0f) - ucf) : 0.0;
+    a.w += in ? (double)(24.0f * ir6 * t) : 0.0;
+  }
+  if (COUNT) a.pc += in ? 1u : 0u;
+}
+
+// The same FP32 pair term, added unconditionally (guard-band pairs found in range).
+template <bool ENERGY, bool COUNT>
+__device__ __forceinline__ void pair32_add(float dx, float dy, float dz, float r2, float ucf, Acc<float>& a) {
+  const float ir2 = __builtin_amdgcn_rcpf(r2);
+  const float ir6 = ir2 * ir2 * ir2;
+  const float t = fmaf(2.0f, ir6, -1.0f);
+  const float fr = 24.0f * ir2 * ir6 * t;
+  a.fx = fmaf(fr, dx, a.fx);
+  a.fy = fmaf(fr, dy, a.fy);
+  a.fz = fmaf(fr, dz, a.fz);
+  if (ENERGY) {
+    a.u += (double)(4.0f * ir6 * (ir6 - 1.0f) - ucf);
+    a.w += (double)(24.0f * ir6 * t);
+  }
+  if (COUNT) a.pc += 1u;
+}
+
+// FP64 pair; WRAP applies the minimum-image rule to every component.
+template <bool ENERGY, bool COUNT, bool WRAP>
+__device__ __forceinline__ void pair64(const DGeom& g, double xi, double yi, double zi, double xj, double yj,
+                                       double zj, Acc<double>& a) {
+  double dx = __dsub_rn(xi, xj), dy = __dsub_rn(yi, yj), dz = __dsub_rn(zi, zj);
+  if (WRAP) {
+    dx = min_img(dx, g.L[0], g.halfL[0]);
+    dy = min_img(dy, g.L[1], g.halfL[1]);
+    dz = min_img(dz, g.L[2], g.halfL[2]);
+  }
+  const double r2 = r2_exact(dx, dy, dz);
+  const bool in = (r2 <= g.rc2) & (r2 > 0.0);
+  const double ir2 = recip64(r2);
+  const double ir6 = ir2 * ir2 * ir2;
+  const double t = fma(2.0, ir6, -1.0);
+  double fr = 24.0 * ir2 * ir6 * t;
+  fr = in ? fr : 0.0;
+  a.fx = fma(fr, dx, a.fx);
+  a.fy = fma(fr, dy, a.fy);
+  a.fz = fma(fr, dz, a.fz);
+  if (ENERGY) {
+    a.u += in ? 4.0 * ir6 * (ir6 - 1.0) - g.uc : 0.0;
+    a.w += in ? 24.0 * ir6 * t : 0.0;
+  }
+  if (COUNT) a.pc += in ? 1u : 0u;
 }
 
 // ---------------------------------------------------------------------------
 // Pair forces of every atom of cell c (Algorithm 1, first loop; kernel md_v3a).
-// Lane layout: P = n atoms x G groups (G = min(16, 64 / n)); lane (ii, grp) sums the
-// candidates grp, grp + G, ... of the 27-cell list for atom ii; the group partials are
-// then added in group order, so every atom's sum has a fixed order.
+//
+// The 27 neighbour cells are flattened into one candidate list (tag table in LDS)
+// and staged tile by tile into LDS.  Each lane holds two atoms of the cell (a and
+// a + P, P = ceil(n/2)) and one of G candidate groups; lane (a, grp) visits
+// candidates grp, grp + G, ... so that one LDS read serves two pairs.  Group partials
+// are added in group order, so every atom's sum has a fixed order.
 // ---------------------------------------------------------------------------
 template <int PREC, bool ENERGY, bool COUNT>
-__device__ void cell_force(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt,
-                           int c, Scratch<PREC>& ws, ForceOut& o) {
+__device__ void cell_force(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int c,
+                           Scratch<PREC>& ws, ForceOut& o) {
+  using R = typename std::conditional<PREC == 1, float, double>::type;
   const int lane = __lane_id();
   const int n_i = (int)ncnt[c];
   o.n = n_i;
@@ -175,192 +262,192 @@ __device__ void cell_force(const DGeom& g, const unsigned char* cells, const uin
     nc = global_cell(g, nx, ny, nz);
     cnt = (int)ncnt[nc];
   }
-  int incl = cnt;
+  int incl = cnt, mx = cnt;
 #pragma unroll
   for (int off = 1; off < 32; off <<= 1) {
-    int v = __shfl_up(incl, off);
+    const int v = __shfl_up(incl, off);
     if (lane >= off) incl += v;
+    mx = max(mx, __shfl_xor(mx, off));
   }
   const int total = __shfl(incl, 26);
   const bool any_wrap = __ballot(wrapped) != 0ull;
+  const int excl = incl - cnt;
   wave_sync();
-  if (lane < 27) {
-    ws.nb_cell[lane] = nc;
-    ws.nb_pre[lane] = incl - cnt;
-  }
-  if (lane == 0) ws.nb_pre[27] = total;
+  if (lane < 27) ws.nb_cell[lane] = nc;
+  for (int k = 0; k < mx; k++)
+    if (lane < 27 && k < cnt) ws.tag[excl + k] = (uint16_t)((lane << 6) | k);
   wave_sync();
   o.total = total;
 
-  const int P = n_i;
+  // lane layout: atoms a and a + P, candidate group grp of G
+  const int P = (n_i + 1) >> 1;
   int G = 64 / P;
   if (G > 16) G = 16;
-  const int ii = lane % P;
+  const int ia = lane % P;
   const int grp = lane / P;
   const bool act = grp < G;
-  const double* ib = cblk(cells, c);
-  const double xi = ib[ii], yi = ib[CELL_CAP + ii], zi = ib[2 * CELL_CAP + ii];
-  const unsigned selftag = make_tag(13, ii);
+  const int ib_ = ia + P;
+  const bool has_b = ib_ < n_i;
+  const double* iblk = cblk(cells, c);
 
-  double uacc = 0.0, wacc = 0.0;
-  unsigned pc = 0;
-  double sfx, sfy, sfz;
+  Acc<R> A, B;
+  acc_init(A);
+  acc_init(B);
 
+  // cell origin (FP32 coordinates are taken relative to it)
+  const double ox = gx * g.l[0], oy = gy * g.l[1], oz = gz * g.l[2];
+  R aix, aiy, aiz, bix, biy, biz;
   if constexpr (PREC == 1) {
-    // FP32 on coordinates relative to the cell's lower corner (|q| < 2 cells).
-    const double ox = gx * g.l[0], oy = gy * g.l[1], oz = gz * g.l[2];
-    const float qix = (float)(xi - ox), qiy = (float)(yi - oy), qiz = (float)(zi - oz);
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int tb = 0; tb < total; tb += TILE) {
-      const int tn = min(TILE, total - tb);
-      wave_sync();
-      for (int e = lane; e < tn; e += 64) {
-        const int f = tb + e;
-        int lo = 0, hi = 27;
-        while (hi - lo > 1) {
-          int mid = (lo + hi) >> 1;
-          if (ws.nb_pre[mid] <= f) lo = mid; else hi = mid;
-        }
-        const int k = f - ws.nb_pre[lo];
-        const double* jb = cblk(cells, ws.nb_cell[lo]);
-        const int nx = gx + lo / 9 - 1, ny = gy + (lo / 3) % 3 - 1, nz = gz + lo % 3 - 1;
-        const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
-        const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
-        const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
-        float4 q;
-        q.x = (float)((jb[k] + shx) - ox);
-        q.y = (float)((jb[CELL_CAP + k] + shy) - oy);
-        q.z = (float)((jb[2 * CELL_CAP + k] + shz) - oz);
-        q.w = __uint_as_float(make_tag(lo, k));
-        ws.q[e] = q;
+    aix = (float)(iblk[ia] - ox);
+    aiy = (float)(iblk[CELL_CAP + ia] - oy);
+    aiz = (float)(iblk[2 * CELL_CAP + ia] - oz);
+    // a missing second atom sits far away and never interacts
+    bix = has_b ? (float)(iblk[ib_] - ox) : 1e30f;
+    biy = has_b ? (float)(iblk[CELL_CAP + ib_] - oy) : 1e30f;
+    biz = has_b ? (float)(iblk[2 * CELL_CAP + ib_] - oz) : 1e30f;
+  } else {
+    aix = iblk[ia];
+    aiy = iblk[CELL_CAP + ia];
+    aiz = iblk[2 * CELL_CAP + ia];
+    bix = has_b ? iblk[ib_] : 1e300;
+    biy = has_b ? iblk[CELL_CAP + ib_] : 1e300;
+    biz = has_b ? iblk[2 * CELL_CAP + ib_] : 1e300;
+  }
+  const unsigned lo_bits = __float_as_uint(g.rc2_lo_f), hi_bits = __float_as_uint(g.rc2_hi_f);
+
+  for (int tb = 0; tb < total; tb += TILE) {
+    const int tn = min(TILE, total - tb);
+    wave_sync();
+    // stage the tile: all loads of a lane are issued before the conversions
+    double sx[TILE / 64], sy[TILE / 64], sz[TILE / 64];
+    int sm[TILE / 64];
+#pragma unroll
+    for (int u = 0; u < TILE / 64; u++) {
+      const int e = lane + 64 * u;
+      sm[u] = 0;
+      sx[u] = sy[u] = sz[u] = 0.0;
+      if (e < tn) {
+        const unsigned tg = ws.tag[tb + e];
+        const int m = (int)(tg >> 6), k = (int)(tg & 63u);
+        const double* jb = cblk(cells, ws.nb_cell[m]);
+        sx[u] = jb[k];
+        sy[u] = jb[CELL_CAP + k];
+        sz[u] = jb[2 * CELL_CAP + k];
+        sm[u] = m;
       }
-      wave_sync();
-      for (int f = act ? grp : tn; f < tn; f += G) {
-        const float4 q = ws.q[f];
-        const float dx = qix - q.x, dy = qiy - q.y, dz = qiz - q.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const unsigned tag = __float_as_uint(q.w);
-        if (r2 <= g.rc2_hi_f && tag != selftag) {
-          bool inr = r2 <= g.rc2_lo_f;
-          if (!inr) inr = exact_in_range(g, xi, yi, zi, cells, ws.nb_cell[tag >> 6], tag & 63u);
-          if (inr) {
-            const float ir2 = __builtin_amdgcn_rcpf(r2);
-            const float ir6 = ir2 * ir2 * ir2;
-            const float t = 2.0f * ir6 - 1.0f;
-            const float fr = 24.0f * ir2 * ir6 * t;
-            fx += fr * dx;
-            fy += fr * dy;
-            fz += fr * dz;
-            if (ENERGY) {
-              uacc += (double)(4.0f * ir6 * (ir6 - 1.0f) - g.uc_f);
-              wacc += (double)(24.0f * ir6 * t);
-            }
-            if (COUNT) pc++;
-          }
+    }
+#pragma unroll
+    for (int u = 0; u < TILE / 64; u++) {
+      const int e = lane + 64 * u;
+      if (e < tn) {
+        if constexpr (PREC == 1) {
+          const int m = sm[u];
+          const int nx = gx + m / 9 - 1, ny = gy + (m / 3) % 3 - 1, nz = gz + m % 3 - 1;
+          const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
+          const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
+          const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
+          ws.q[e] = make_float4((float)((sx[u] + shx) - ox), (float)((sy[u] + shy) - oy),
+                                (float)((sz[u] + shz) - oz), 0.0f);
+        } else {
+          ws.t.x[e] = sx[u];
+          ws.t.y[e] = sy[u];
+          ws.t.z[e] = sz[u];
         }
       }
     }
-    sfx = fx;
-    sfy = fy;
-    sfz = fz;
-  } else {
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int tb = 0; tb < total; tb += TILE) {
-      const int tn = min(TILE, total - tb);
-      wave_sync();
-      for (int e = lane; e < tn; e += 64) {
-        const int f = tb + e;
-        int lo = 0, hi = 27;
-        while (hi - lo > 1) {
-          int mid = (lo + hi) >> 1;
-          if (ws.nb_pre[mid] <= f) lo = mid; else hi = mid;
-        }
-        const int k = f - ws.nb_pre[lo];
-        const double* jb = cblk(cells, ws.nb_cell[lo]);
-        ws.t.x[e] = jb[k];
-        ws.t.y[e] = jb[CELL_CAP + k];
-        ws.t.z[e] = jb[2 * CELL_CAP + k];
-        ws.tag[e] = make_tag(lo, k);
+    wave_sync();
+    const int f0 = act ? grp : tn;
+    if constexpr (PREC == 1) {
+#pragma unroll 2
+      for (int f = f0; f < tn; f += G) {
+        const float4 q = ws.q[f];
+        pair32<ENERGY, COUNT>(aix, aiy, aiz, q, lo_bits, hi_bits, g.uc_f, A);
+        pair32<ENERGY, COUNT>(bix, biy, biz, q, lo_bits, hi_bits, g.uc_f, B);
       }
-      wave_sync();
-      if (!any_wrap) {
-        // no periodic neighbour: the raw difference is the minimum image of every
-        // pair that can be in range
-        for (int f = act ? grp : tn; f < tn; f += G) {
-          const double dx = __dsub_rn(xi, ws.t.x[f]);
-          const double dy = __dsub_rn(yi, ws.t.y[f]);
-          const double dz = __dsub_rn(zi, ws.t.z[f]);
-          const double r2 = r2_exact(dx, dy, dz);
-          if (r2 <= g.rc2 && ws.tag[f] != selftag) {
-            const double ir2 = 1.0 / r2;
-            const double ir6 = ir2 * ir2 * ir2;
-            const double t = 2.0 * ir6 - 1.0;
-            const double fr = 24.0 * ir2 * ir6 * t;
-            fx += fr * dx;
-            fy += fr * dy;
-            fz += fr * dz;
-            if (ENERGY) {
-              uacc += 4.0 * ir6 * (ir6 - 1.0) - g.uc;
-              wacc += 24.0 * ir6 * t;
+      // guard band: decide those pairs in FP64 exactly as the FP64 path would
+      if (__ballot(A.band || B.band)) {
+        for (int h = 0; h < 2; h++) {
+          Acc<float>& X = h == 0 ? A : B;
+          if (!X.band) continue;
+          const int a = h == 0 ? ia : ib_;
+          const float qx = h == 0 ? aix : bix, qy = h == 0 ? aiy : biy, qz = h == 0 ? aiz : biz;
+          const double xi = iblk[a], yi = iblk[CELL_CAP + a], zi = iblk[2 * CELL_CAP + a];
+          for (int f = f0; f < tn; f += G) {
+            const float4 q = ws.q[f];
+            const float dx = qx - q.x, dy = qy - q.y, dz = qz - q.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const unsigned rb = __float_as_uint(r2) - 1u;
+            if (rb >= lo_bits && rb < hi_bits) {
+              const unsigned tg = ws.tag[tb + f];
+              const double* jb = cblk(cells, ws.nb_cell[tg >> 6]);
+              const int k = (int)(tg & 63u);
+              const double ex = min_img(__dsub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
+              const double ey = min_img(__dsub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
+              const double ez = min_img(__dsub_rn(zi, jb[2 * CELL_CAP + k]), g.L[2], g.halfL[2]);
+              if (r2_exact(ex, ey, ez) <= g.rc2) pair32_add<ENERGY, COUNT>(dx, dy, dz, r2, g.uc_f, X);
             }
-            if (COUNT) pc++;
           }
+          X.band = false;
+        }
+      }
+    } else {
+      if (!any_wrap) {
+#pragma unroll 2
+        for (int f = f0; f < tn; f += G) {
+          const double xj = ws.t.x[f], yj = ws.t.y[f], zj = ws.t.z[f];
+          pair64<ENERGY, COUNT, false>(g, aix, aiy, aiz, xj, yj, zj, A);
+          pair64<ENERGY, COUNT, false>(g, bix, biy, biz, xj, yj, zj, B);
         }
       } else {
-        for (int f = act ? grp : tn; f < tn; f += G) {
-          const double dx = min_img(__dsub_rn(xi, ws.t.x[f]), g.L[0], g.halfL[0]);
-          const double dy = min_img(__dsub_rn(yi, ws.t.y[f]), g.L[1], g.halfL[1]);
-          const double dz = min_img(__dsub_rn(zi, ws.t.z[f]), g.L[2], g.halfL[2]);
-          const double r2 = r2_exact(dx, dy, dz);
-          if (r2 <= g.rc2 && ws.tag[f] != selftag) {
-            const double ir2 = 1.0 / r2;
-            const double ir6 = ir2 * ir2 * ir2;
-            const double t = 2.0 * ir6 - 1.0;
-            const double fr = 24.0 * ir2 * ir6 * t;
-            fx += fr * dx;
-            fy += fr * dy;
-            fz += fr * dz;
-            if (ENERGY) {
-              uacc += 4.0 * ir6 * (ir6 - 1.0) - g.uc;
-              wacc += 24.0 * ir6 * t;
-            }
-            if (COUNT) pc++;
-          }
+        for (int f = f0; f < tn; f += G) {
+          const double xj = ws.t.x[f], yj = ws.t.y[f], zj = ws.t.z[f];
+          pair64<ENERGY, COUNT, true>(g, aix, aiy, aiz, xj, yj, zj, A);
+          pair64<ENERGY, COUNT, true>(g, bix, biy, biz, xj, yj, zj, B);
         }
       }
     }
-    sfx = fx;
-    sfy = fy;
-    sfz = fz;
   }
 
-  // add the group partials of each atom in group order
-  wave_sync();
+  // add the group partials of each atom in group order (first the a atoms, then the b)
+  double sa[6] = {0, 0, 0, 0, 0, 0}, sb[6] = {0, 0, 0, 0, 0, 0};
   double* red = ws.red;
-  red[lane * 6 + 0] = sfx;
-  red[lane * 6 + 1] = sfy;
-  red[lane * 6 + 2] = sfz;
-  red[lane * 6 + 3] = uacc;
-  red[lane * 6 + 4] = wacc;
-  red[lane * 6 + 5] = (double)pc;
+  for (int h = 0; h < 2; h++) {
+    const Acc<R>& X = h == 0 ? A : B;
+    wave_sync();
+    red[lane * 6 + 0] = (double)X.fx;
+    red[lane * 6 + 1] = (double)X.fy;
+    red[lane * 6 + 2] = (double)X.fz;
+    red[lane * 6 + 3] = X.u;
+    red[lane * 6 + 4] = X.w;
+    red[lane * 6 + 5] = (double)X.pc;
+    wave_sync();
+    if (lane < P) {
+      double* s = h == 0 ? sa : sb;
+      for (int q = 0; q < G; q++) {
+        const double* r = red + (lane + q * P) * 6;
+#pragma unroll
+        for (int v = 0; v < 6; v++) s[v] += r[v];
+      }
+    }
+  }
   wave_sync();
   if (lane < P) {
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
-    for (int q = 0; q < G; q++) {
-      const double* r = red + (lane + q * P) * 6;
-      a0 += r[0];
-      a1 += r[1];
-      a2 += r[2];
-      a3 += r[3];
-      a4 += r[4];
-      a5 += r[5];
+#pragma unroll
+    for (int v = 0; v < 6; v++) red[lane * 6 + v] = sa[v];
+    if (lane + P < n_i) {
+#pragma unroll
+      for (int v = 0; v < 6; v++) red[(lane + P) * 6 + v] = sb[v];
     }
-    o.fx = a0;
-    o.fy = a1;
-    o.fz = a2;
-    o.uh = 0.5 * a3;
-    o.wh = 0.5 * a4;
-    o.pc = (unsigned)a5;
+  }
+  wave_sync();
+  if (lane < n_i) {
+    const double* r = red + lane * 6;
+    o.fx = r[0];
+    o.fy = r[1];
+    o.fz = r[2];
+    o.uh = 0.5 * r[3];
+    o.wh = 0.5 * r[4];
+    o.pc = (unsigned)r[5];
   }
   wave_sync();
 }
@@ -536,16 +623,35 @@ __device__ void p1_range(const RunArgs& ra, int b, int e, int dst, int wave, uin
 }
 
 // ---------------------------------------------------------------------------
-// Persistent kernel: claims tickets in order; ticket -> (round k, run, item); an item
-// waits on the per-slice counters of its two neighbours and itself, runs, publishes.
-//   force/integrate item of slice i at step k: needs finalise(i-1, i, i+1) of step k;
-//   finalise item of slice i for step k+1:     needs integrate(i-1, i, i+1) of step k.
-// The claim order only sets which ready item a workgroup takes next; dependencies
-// always point to smaller tickets, so every wait ends.
+// Persistent kernel.
+//   force/integrate item (phase 0) of slice i at step k needs the finalise items of
+//   slices i-1, i, i+1 for step k; the finalise item (phase 1) of slice i for step
+//   k+1 needs the force/integrate items of i-1, i, i+1 at step k.
+// Two schedulers share the item bodies:
+//   dataflow (default): the item that completes a dependency set appends the now
+//     ready items to a queue; workers take queue slots in order, so nobody holds an
+//     item whose inputs are missing;
+//   ticket: items are dealt in a fixed per-step order (claim-order tables) and wait
+//     on the per-slice counters of their neighbours.
+// Both end: every item is pushed (dealt) exactly once and its dependencies were
+// pushed (dealt) before it.
 // ---------------------------------------------------------------------------
 struct Item {
   int run, k, phase, slice, chunk, go;
 };
+
+__device__ __forceinline__ unsigned long long enc_item(int run, int k, int phase, int slice, int chunk) {
+  return (1ull << 63) | ((unsigned long long)run << 48) | ((unsigned long long)k << 28) |
+         ((unsigned long long)phase << 27) | ((unsigned long long)slice << 12) | (unsigned long long)chunk;
+}
+
+__device__ __forceinline__ void dec_item(unsigned long long v, Item& it) {
+  it.run = (int)((v >> 48) & 0x7fffull);
+  it.k = (int)((v >> 28) & 0xfffffull);
+  it.phase = (int)((v >> 27) & 1ull);
+  it.slice = (int)((v >> 12) & 0x7fffull);
+  it.chunk = (int)(v & 0xfffull);
+}
 
 __device__ bool wait_counters(const LaunchArgs& la, const uint32_t* cnt, int S, int s, unsigned need,
                               uint32_t* err, uint32_t* abort_flag) {
@@ -640,81 +746,156 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, Scratch<PREC>& ws
   }
 }
 
-template <int PREC>
+template <int PREC, bool FULL>
+__device__ void run_item(const RunArgs& ra, const Item& it, Scratch<PREC>& ws, double (*s_red)[3],
+                         unsigned long long (*s_cnt)[4]) {
+  const int wave = threadIdx.x >> 6;
+  if (it.phase == 0) {
+    const long long t = ra.t0 + it.k;
+    const bool energy = ra.every > 0 && (t % ra.every) == 0;
+    if (!FULL) {
+      run_p2_item<PREC, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+    } else if (ra.count) {
+      if (energy) run_p2_item<PREC, true, true>(ra, it, ws, s_red, s_cnt, ra.abort);
+      else run_p2_item<PREC, false, true>(ra, it, ws, s_red, s_cnt, ra.abort);
+    } else {
+      if (energy) run_p2_item<PREC, true, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+      else run_p2_item<PREC, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+    }
+  } else {
+    const int dst = (ra.par0 + it.k + 1) & 1;
+    const int b = (int)((long long)ra.g.cps * it.chunk / ra.nch);
+    const int e = (int)((long long)ra.g.cps * (it.chunk + 1) / ra.nch);
+    const int cbase = it.slice * ra.g.cps;
+    p1_range(ra, cbase + b, cbase + e, dst, wave, ra.abort);
+  }
+}
+
+// Dataflow completion: count this item towards its dependents; the count that completes
+// a dependency set appends the dependent items (all chunks) to the queue.
+__device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const Item& it) {
+  const int S = ra.g.S;
+  const unsigned need = 3u * (unsigned)ra.nch * (unsigned)(it.k + 1);
+  uint32_t* cnt = it.phase == 0 ? ra.cntF : ra.cntA;
+  for (int d = -1; d <= 1; d++) {
+    const int j = (it.slice + d + S) % S;
+    const unsigned old = __hip_atomic_fetch_add(cnt + j, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1u != need) continue;
+    int phase, k;
+    if (it.phase == 0) {
+      phase = 1;  // finalise of step k+1
+      k = it.k;
+    } else {
+      if (it.k + 1 >= ra.nsteps) continue;  // the launch ends with this finalise
+      phase = 0;
+      k = it.k + 1;
+    }
+    const unsigned long long base =
+        __hip_atomic_fetch_add(la.q_tail, (unsigned long long)ra.nch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int ch = 0; ch < ra.nch; ch++)
+      __hip_atomic_store(la.q + base + ch, enc_item(it.run, k, phase, j, ch), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// FULL = false: launches without energy samples or pair counting (fewer registers).
+template <int PREC, bool FULL>
 __global__ __launch_bounds__(WG) void persistent_kernel(LaunchArgs la) {
   __shared__ Scratch<PREC> ws[WAVES];
   __shared__ double s_red[WAVES][3];
   __shared__ unsigned long long s_cnt[WAVES][4];
   __shared__ Item s_it;
   __shared__ int s_ok;
+  __shared__ long long s_ticket;
   const int wave = threadIdx.x >> 6;
-  const long long total = la.round_base[la.nrounds];
+  const long long total = la.total;
   while (true) {
     if (threadIdx.x == 0) {
       Item it;
       it.go = 0;
       const long long T = (long long)atomicAdd(la.ticket, 1ull);
+      s_ticket = T;
+      if (la.trace && T < total) la.trace[T].t_claim = wall_clock64();
       if (T < total) {
-        int lo = 0, hi = la.nrounds;
-        while (hi - lo > 1) {
-          int mid = (lo + hi) >> 1;
-          if (la.round_base[mid] <= T) lo = mid; else hi = mid;
+        if (la.mode == 0) {
+          // dataflow: wait for slot T to be filled
+          const long long t_begin = wall_clock64();
+          unsigned long long v;
+          while (!((v = __hip_atomic_load(la.q + T, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) >> 63)) {
+            if (ld_relaxed(la.launch_err)) break;
+            if (wall_clock64() - t_begin > la.watchdog_ticks) {
+              raise_error(la.launch_err, nullptr, ERR_WATCHDOG);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          if (v >> 63) {
+            dec_item(v, it);
+            it.go = 1;
+          }
+        } else {
+          int lo = 0, hi = la.nrounds;
+          while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (la.round_base[mid] <= T) lo = mid; else hi = mid;
+          }
+          const int k = lo;
+          const long long rem = T - la.round_base[k];
+          int rlo = 0, rhi = la.round_active[k];
+          while (rhi - rlo > 1) {
+            int mid = (rlo + rhi) >> 1;
+            if (la.run_prefix[mid] <= rem) rlo = mid; else rhi = mid;
+          }
+          const RunArgs& ra = la.runs[rlo];
+          const int local = (int)(rem - la.run_prefix[rlo]);
+          const int entry = local / ra.nch;
+          const unsigned ord = ra.order[entry];
+          it.run = rlo;
+          it.k = k;
+          it.phase = (int)(ord >> 15);
+          it.slice = (int)(ord & 0x7fffu);
+          it.chunk = local - entry * ra.nch;
+          it.go = 1;
         }
-        const int k = lo;
-        const long long rem = T - la.round_base[k];
-        int rlo = 0, rhi = la.round_active[k];
-        while (rhi - rlo > 1) {
-          int mid = (rlo + rhi) >> 1;
-          if (la.run_prefix[mid] <= rem) rlo = mid; else rhi = mid;
-        }
-        const RunArgs& ra = la.runs[rlo];
-        const int local = (int)(rem - la.run_prefix[rlo]);
-        const int entry = local / ra.nch;
-        const unsigned ord = ra.order[entry];
-        it.run = rlo;
-        it.k = k;
-        it.phase = (int)(ord >> 15);
-        it.slice = (int)(ord & 0x7fffu);
-        it.chunk = local - entry * ra.nch;
-        it.go = 1;
       }
       s_it = it;
     }
     __syncthreads();
     const Item it = s_it;
     if (it.go == 0) break;
-    if (it.go == 1) {
-      const RunArgs& ra = la.runs[it.run];
-      if (threadIdx.x == 0) {
+    const RunArgs& ra = la.runs[it.run];
+    if (threadIdx.x == 0) {
+      bool ok = !ld_relaxed(ra.abort);
+      if (la.mode != 0 && ok) {
         const unsigned need = (unsigned)(it.k + 1) * (unsigned)ra.nch;
-        s_ok = !ld_relaxed(ra.abort) &&
-               wait_counters(la, it.phase == 0 ? ra.cntA : ra.cntF, ra.g.S, it.slice, need, ra.err, ra.abort);
+        ok = wait_counters(la, it.phase == 0 ? ra.cntA : ra.cntF, ra.g.S, it.slice, need, ra.err, ra.abort);
       }
-      __syncthreads();
-      const int ok = s_ok;
-      if (ok) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (it.phase == 0) {
-          const long long t = ra.t0 + it.k;
-          const bool energy = ra.every > 0 && (t % ra.every) == 0;
-          if (ra.count) {
-            if (energy) run_p2_item<PREC, true, true>(ra, it, ws[wave], s_red, s_cnt, ra.abort);
-            else run_p2_item<PREC, false, true>(ra, it, ws[wave], s_red, s_cnt, ra.abort);
-          } else {
-            if (energy) run_p2_item<PREC, true, false>(ra, it, ws[wave], s_red, s_cnt, ra.abort);
-            else run_p2_item<PREC, false, false>(ra, it, ws[wave], s_red, s_cnt, ra.abort);
-          }
-        } else {
-          const int dst = (ra.par0 + it.k + 1) & 1;
-          const int b = (int)((long long)ra.g.cps * it.chunk / ra.nch);
-          const int e = (int)((long long)ra.g.cps * (it.chunk + 1) / ra.nch);
-          const int cbase = it.slice * ra.g.cps;
-          p1_range(ra, cbase + b, cbase + e, dst, wave, ra.abort);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      s_ok = ok;
+      if (la.trace) {
+        TraceRec& tr = la.trace[s_ticket];
+        tr.t_ready = wall_clock64();
+        tr.k = (uint32_t)it.k;
+        tr.slice = (uint32_t)it.slice;
+        tr.chunk = (uint32_t)it.chunk;
+        tr.phase = (uint32_t)it.phase;
+        tr.hw_id = __smid();
+        tr.launch = la.launch_index;
       }
-      __syncthreads();
-      if (ok && threadIdx.x == 0) {
+    }
+    __syncthreads();
+    const int ok = s_ok;
+    if (ok) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      run_item<PREC, FULL>(ra, it, ws[wave], s_red, s_cnt);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (la.trace) la.trace[s_ticket].t_done = wall_clock64();
+      if (la.mode == 0) {
+        // an aborted run still completes its items (without work) so the queue drains
+        complete_dataflow(la, ra, it);
+      } else if (ok) {
         uint32_t* cnt = it.phase == 0 ? ra.cntF : ra.cntA;
         __hip_atomic_fetch_add(cnt + it.slice, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -723,20 +904,31 @@ __global__ __launch_bounds__(WG) void persistent_kernel(LaunchArgs la) {
   }
 }
 
-// Counters at the start of a launch: every slice is finalised for its first step
-// (cntA = nch), nothing integrated yet (cntF = 0).
-__global__ void init_counters_kernel(RunArgs* runs, int nruns, int max_slices,
-                                     unsigned long long* ticket) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *ticket = 0ull;
-  for (int r = 0; r < nruns; r++) {
-    if (i == 0) *runs[r].abort = 0u;
-    if (i < runs[r].g.S) {
-      runs[r].cntA[i] = (uint32_t)runs[r].nch;
-      runs[r].cntF[i] = 0u;
+// Launch set-up: counters, abort flags, claim counter; in dataflow mode the queue holds
+// the force/integrate items of the first step of every run.
+__global__ void init_launch_kernel(LaunchArgs la) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  if (i == 0) {
+    *la.ticket = 0ull;
+    if (la.launch_err) *la.launch_err = 0u;
+  }
+  long long base = 0;
+  for (int r = 0; r < la.nruns; r++) {
+    const RunArgs& ra = la.runs[r];
+    if (i == 0) *ra.abort = 0u;
+    for (long long s = i; s < ra.g.S; s += stride) {
+      ra.cntA[s] = la.mode == 0 ? 0u : (uint32_t)ra.nch;
+      ra.cntF[s] = 0u;
+    }
+    if (la.mode == 0 && ra.nsteps > 0) {
+      const long long n0 = (long long)ra.g.S * ra.nch;
+      for (long long e = i; e < n0; e += stride)
+        la.q[base + e] = enc_item(r, 0, 0, (int)(e / ra.nch), (int)(e % ra.nch));
+      base += n0;
     }
   }
-  (void)max_slices;
+  if (i == 0 && la.q_tail) *la.q_tail = (unsigned long long)base;
 }
 
 // ---------------------------------------------------------------------------
@@ -900,34 +1092,38 @@ int launch_sort_cells(const DGeom& g, unsigned char* cells, uint32_t* ncnt, uint
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_init_counters(RunArgs* runs_dev, int nruns, int max_slices, unsigned long long* ticket,
-                         void* stream) {
-  const int blocks = (max_slices + 255) / 256;
-  hipLaunchKernelGGL(init_counters_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, S_(stream),
-                     runs_dev, nruns, max_slices, ticket);
+int launch_init(const LaunchArgs& la, long long work, void* stream) {
+  hipLaunchKernelGGL(init_launch_kernel, dim3(grid_for(work, 256)), dim3(256), 0, S_(stream), la);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int persistent_grid(int prec, int* blocks_per_cu, int* cus) {
+int persistent_grid(int prec, int full, int* blocks_per_cu, int* cus) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
   int nb = 0;
-  hipError_t e = prec == 1
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<1>, WG, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<0>, WG, 0);
+  hipError_t e;
+  if (prec == 1)
+    e = full ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<1, true>, WG, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<1, false>, WG, 0);
+  else
+    e = full ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<0, true>, WG, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<0, false>, WG, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   *blocks_per_cu = nb;
   *cus = prop.multiProcessorCount;
   return 0;
 }
 
-int launch_persistent(const LaunchArgs& la, int prec, int grid, void* stream) {
-  if (prec == 1)
-    hipLaunchKernelGGL(persistent_kernel<1>, dim3(grid), dim3(WG), 0, S_(stream), la);
-  else
-    hipLaunchKernelGGL(persistent_kernel<0>, dim3(grid), dim3(WG), 0, S_(stream), la);
+int launch_persistent(const LaunchArgs& la, int prec, int full, int grid, void* stream) {
+  if (prec == 1) {
+    if (full) hipLaunchKernelGGL((persistent_kernel<1, true>), dim3(grid), dim3(WG), 0, S_(stream), la);
+    else hipLaunchKernelGGL((persistent_kernel<1, false>), dim3(grid), dim3(WG), 0, S_(stream), la);
+  } else {
+    if (full) hipLaunchKernelGGL((persistent_kernel<0, true>), dim3(grid), dim3(WG), 0, S_(stream), la);
+    else hipLaunchKernelGGL((persistent_kernel<0, false>), dim3(grid), dim3(WG), 0, S_(stream), la);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

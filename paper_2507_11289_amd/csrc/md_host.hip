@@ -274,11 +274,17 @@ struct LaunchScratch {
   size_t round_cap = 0;
   long long* d_run_prefix = nullptr;
   unsigned long long* d_ticket = nullptr;
+  unsigned long long* d_q = nullptr;
+  size_t q_cap = 0;
+  unsigned long long* d_q_tail = nullptr;
+  uint32_t* d_launch_err = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
 
   int reserve(size_t nruns, size_t nrounds) {
     int rc;
     if (!d_ticket && (rc = dalloc(&d_ticket, 1))) return rc;
+    if (!d_q_tail && (rc = dalloc(&d_q_tail, 1))) return rc;
+    if (!d_launch_err && (rc = dalloc(&d_launch_err, 1))) return rc;
     if (nruns > runs_cap) {
       dfree(d_runs);
       dfree(d_run_prefix);
@@ -299,6 +305,10 @@ struct LaunchScratch {
     dfree(d_round_active);
     dfree(d_run_prefix);
     dfree(d_ticket);
+    dfree(d_q);
+    dfree(d_q_tail);
+    dfree(d_launch_err);
+    q_cap = 0;
     for (int i = 0; i < 2; i++)
       if (ev[i]) (void)hipEventDestroy(ev[i]);
     ev[0] = ev[1] = nullptr;
@@ -321,7 +331,7 @@ struct md_sim {
   hipStream_t stream = nullptr;
   // options
   int64_t every = 0;
-  int order_kind = MD_ORDER_SWEEP;
+  int order_kind = MD_ORDER_DATAFLOW;
   uint64_t order_seed = 1;
   bool order_dirty = true;
   bool miglog_on = false;
@@ -331,6 +341,10 @@ struct md_sim {
   int64_t grid_override = 0;
   int64_t fail_at = -1;
   int64_t max_steps_per_launch = 4096;
+  bool trace_on = false;
+  std::vector<TraceRec> trace;
+  TraceRec* d_trace = nullptr;
+  size_t trace_cap = 0;
   int nch = 1;
   // last md_step
   std::vector<double> elog;
@@ -376,7 +390,8 @@ static void free_launch_scratch(md_sim* s) {
   }
   dfree(s->d_epart);
   dfree(s->d_miglog);
-  s->epart_cap = s->miglog_cap = 0;
+  dfree(s->d_trace);
+  s->epart_cap = s->miglog_cap = s->trace_cap = 0;
 }
 
 extern "C" void md_free(md_sim* s) {
@@ -429,7 +444,7 @@ extern "C" int md_set_option(md_sim* s, int key, int64_t value) {
       s->every = value;
       return MD_OK;
     case MD_OPT_CLAIM_ORDER:
-      if (value < MD_ORDER_SWEEP || value > MD_ORDER_RANDOM) return fail(MD_EINVAL, "unknown claim order");
+      if (value < MD_ORDER_SWEEP || value > MD_ORDER_DATAFLOW) return fail(MD_EINVAL, "unknown claim order");
       s->order_kind = (int)value;
       s->order_dirty = true;
       return MD_OK;
@@ -458,6 +473,9 @@ extern "C" int md_set_option(md_sim* s, int key, int64_t value) {
       return MD_OK;
     case MD_OPT_FAIL_AT_STEP:
       s->fail_at = value;
+      return MD_OK;
+    case MD_OPT_TRACE:
+      s->trace_on = value != 0;
       return MD_OK;
     case MD_OPT_MAX_STEPS_PER_LAUNCH:
       if (value <= 0) return fail(MD_EINVAL, "max steps per launch must be > 0");
@@ -581,10 +599,10 @@ extern "C" int md_load(md_sim* s, int64_t n, const double* pos, const double* ve
 // launch; tickets are dealt round by round (round k holds step k of every run that
 // still has steps), so a small run is never starved by a large one.
 // ---------------------------------------------------------------------------
-static int grid_size(int prec, int64_t override_) {
+static int grid_size(int prec, int full, int64_t override_) {
   if (override_ > 0) return (int)override_;
   int bpc = 1, cus = 1;
-  if (persistent_grid(prec, &bpc, &cus)) return 256;
+  if (persistent_grid(prec, full, &bpc, &cus)) return 256;
   return bpc * cus;
 }
 
@@ -603,7 +621,8 @@ static int prepare_run(md_sim* s, int64_t k_steps, hipStream_t st, RunArgs* ra, 
   const DGeom& g = s->g;
   int rc;
   if (s->order_dirty) {
-    std::vector<uint16_t> ord = make_order(g.S, s->order_kind, s->order_seed);
+    std::vector<uint16_t> ord =
+        make_order(g.S, s->order_kind == MD_ORDER_DATAFLOW ? MD_ORDER_SWEEP : s->order_kind, s->order_seed);
     HIPCHK(hipMemcpy(s->b.order, ord.data(), ord.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
     s->order_dirty = false;
   }
@@ -705,7 +724,8 @@ static int finish_run(md_sim* s, int64_t k_steps, int64_t nsample, int64_t first
 // persistent kernel.  status[r] receives each run's own result.
 static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& ksteps, LaunchScratch& ls,
                          hipStream_t st, int64_t grid_override, int64_t watchdog_ms, int* last_grid,
-                         std::vector<int>& status, double* kernel_seconds = nullptr) {
+                         std::vector<int>& status, double* kernel_seconds = nullptr,
+                         md_sim* trace_owner = nullptr, uint32_t launch_index = 0) {
   const size_t R = sims.size();
   status.assign(R, MD_OK);
   if (R == 0) return MD_OK;
@@ -740,7 +760,18 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   HIPCHK(hipMemcpy(ls.d_run_prefix, prefix.data(), prefix.size() * sizeof(long long), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(ls.d_round_base, rb.data(), rb.size() * sizeof(long long), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(ls.d_round_active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice));
-  if (launch_init_counters(ls.d_runs, (int)R, max_slices, ls.d_ticket, st)) return fail(MD_EHIP, "init failed");
+  const int mode = sims[idx[0]]->order_kind == MD_ORDER_DATAFLOW ? 0 : 1;
+  const size_t total = (size_t)rb[(size_t)nrounds];
+  if (nrounds >= (1 << 20)) return fail(MD_EINVAL, "too many steps in one launch");
+  if (mode == 0) {
+    if (total > ls.q_cap) {
+      dfree(ls.d_q);
+      if ((rc = dalloc(&ls.d_q, total))) return rc;
+      ls.q_cap = total;
+    }
+    if (launch_clear_u32(reinterpret_cast<uint32_t*>(ls.d_q), (long long)(2 * total), 0u, st))
+      return fail(MD_EHIP, "clear failed");
+  }
   LaunchArgs la{};
   la.runs = ls.d_runs;
   la.nruns = (int)R;
@@ -750,20 +781,55 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   la.run_prefix = ls.d_run_prefix;
   la.ticket = ls.d_ticket;
   la.watchdog_ticks = watchdog_ticks(watchdog_ms);
-  const int grid = grid_size(prec, grid_override);
+  la.trace = nullptr;
+  la.launch_index = launch_index;
+  la.mode = mode;
+  la.q = mode == 0 ? ls.d_q : nullptr;
+  la.q_tail = ls.d_q_tail;
+  la.launch_err = ls.d_launch_err;
+  la.total = (long long)total;
+  long long prefill = 0;
+  for (size_t q = 0; q < R; q++) prefill += (long long)ra[q].g.S * ra[q].nch;
+  if (trace_owner && trace_owner->trace_on) {
+    if (total > trace_owner->trace_cap) {
+      dfree(trace_owner->d_trace);
+      if ((rc = dalloc(&trace_owner->d_trace, total))) return rc;
+      trace_owner->trace_cap = total;
+    }
+    if (launch_clear_u32(reinterpret_cast<uint32_t*>(trace_owner->d_trace),
+                         (long long)(total * sizeof(TraceRec) / 4), 0u, st))
+      return fail(MD_EHIP, "clear failed");
+    la.trace = trace_owner->d_trace;
+  }
+  if (launch_init(la, std::max<long long>(prefill, max_slices), st)) return fail(MD_EHIP, "init failed");
+  int full = 0;
+  for (size_t q = 0; q < R; q++)
+    if (ra[q].count || nsample[idx[q]] > 0 || ra[q].fail_at >= 0) full = 1;
+  const int grid = grid_size(prec, full, grid_override);
   if (last_grid) *last_grid = grid;
   if (!ls.ev[0]) {
     HIPCHK(hipEventCreate(&ls.ev[0]));
     HIPCHK(hipEventCreate(&ls.ev[1]));
   }
   HIPCHK(hipEventRecord(ls.ev[0], st));
-  if (launch_persistent(la, prec, grid, st)) return fail(MD_EHIP, "persistent launch failed");
+  if (launch_persistent(la, prec, full, grid, st)) return fail(MD_EHIP, "persistent launch failed");
   HIPCHK(hipEventRecord(ls.ev[1], st));
   HIPCHK(hipStreamSynchronize(st));
   if (kernel_seconds) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, ls.ev[0], ls.ev[1]));
     *kernel_seconds = 1e-3 * (double)ms;
+  }
+  if (la.trace) {
+    const size_t off = trace_owner->trace.size();
+    trace_owner->trace.resize(off + total);
+    HIPCHK(hipMemcpy(trace_owner->trace.data() + off, la.trace, total * sizeof(TraceRec), hipMemcpyDeviceToHost));
+  }
+  uint32_t lerr = 0;
+  HIPCHK(hipMemcpy(&lerr, ls.d_launch_err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  if (lerr) {
+    for (size_t r = 0; r < R; r++) status[r] = fail(MD_EWATCHDOG, "a work-queue wait exceeded the watchdog");
+    return MD_OK;
   }
   for (size_t r = 0; r < R; r++) status[r] = finish_run(sims[r], ksteps[r], nsample[r], first_j[r]);
   return MD_OK;
@@ -780,6 +846,7 @@ extern "C" int md_step(md_sim* s, int64_t nsteps) {
   s->cand = s->inr = s->counted = 0;
   s->last_kernel_seconds = 0;
   s->last_launches = 0;
+  s->trace.clear();
   const auto t0 = std::chrono::steady_clock::now();
   int64_t left = nsteps;
   std::vector<md_sim*> one(1, s);
@@ -789,7 +856,7 @@ extern "C" int md_step(md_sim* s, int64_t nsteps) {
     ks[0] = std::min(left, s->max_steps_per_launch);
     double ksec = 0;
     int rc = packed_launch(one, ks, *s->ls, s->stream, s->grid_override, s->watchdog_ms, &s->last_grid, st,
-                           &ksec);
+                           &ksec, s, (uint32_t)s->last_launches);
     s->last_kernel_seconds += ksec;
     s->last_launches++;
     if (!rc) rc = st[0];
@@ -909,6 +976,23 @@ extern "C" int md_get_migration_log(md_sim* s, int64_t cap_steps, int32_t* log, 
   const int64_t m = std::min(s->miglog_steps, cap_steps);
   if (m > 0) std::memcpy(log, s->miglog.data(), sizeof(int32_t) * 2 * s->g.S * (size_t)m);
   *steps = s->miglog_steps;
+  return MD_OK;
+}
+
+extern "C" int md_get_trace(md_sim* s, int64_t cap, md_trace_rec* out, int64_t* count, double* hz) {
+  static_assert(sizeof(md_trace_rec) == sizeof(TraceRec), "trace record layout");
+  if (!s || !count || cap < 0 || (cap > 0 && !out)) return fail(MD_EINVAL, "bad arguments");
+  const int64_t have = (int64_t)s->trace.size();
+  const int64_t m = std::min(have, cap);
+  if (m > 0) std::memcpy(out, s->trace.data(), sizeof(TraceRec) * (size_t)m);
+  *count = have;
+  if (hz) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+      khz = 100000;
+    *hz = 1e3 * khz;
+  }
   return MD_OK;
 }
 

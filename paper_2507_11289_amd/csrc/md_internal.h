@@ -72,6 +72,12 @@ struct RunArgs {
   int ips;                      // items per step = 2 * S * nch
 };
 
+struct TraceRec {
+  uint32_t k, slice, chunk, phase;
+  uint32_t hw_id, launch;
+  unsigned long long t_claim, t_ready, t_done;
+};
+
 struct LaunchArgs {
   RunArgs* runs;
   int nruns;
@@ -81,6 +87,13 @@ struct LaunchArgs {
   const long long* run_prefix;  // [nruns + 1] prefix sums of ips
   unsigned long long* ticket;   // claim counter
   long long watchdog_ticks;     // wall_clock64 ticks a wait may take
+  TraceRec* trace;              // one record per ticket, or null
+  uint32_t launch_index;
+  int mode;                     // 0 dataflow queue, 1 fixed claim order
+  unsigned long long* q;        // dataflow: item slots (top bit set once pushed)
+  unsigned long long* q_tail;   // dataflow: next free slot
+  uint32_t* launch_err;         // dataflow: a queue wait exceeded the watchdog
+  long long total;              // items in the launch
 };
 
 // Host-callable launch wrappers (defined in md_device.hip).
@@ -89,10 +102,9 @@ int launch_load_scatter(const DGeom& g, const double* pos, const double* vel, lo
                         unsigned char* cells, uint32_t* ncnt, uint32_t* err, void* stream);
 int launch_sort_cells(const DGeom& g, unsigned char* cells, uint32_t* ncnt, uint32_t* err,
                       void* stream);
-int launch_init_counters(RunArgs* runs_dev, int nruns, int max_slices, unsigned long long* ticket,
-                         void* stream);
-int persistent_grid(int prec, int* blocks_per_cu, int* cus);
-int launch_persistent(const LaunchArgs& la, int prec, int grid, void* stream);
+int launch_init(const LaunchArgs& la, long long work, void* stream);
+int persistent_grid(int prec, int full, int* blocks_per_cu, int* cus);
+int launch_persistent(const LaunchArgs& la, int prec, int full, int grid, void* stream);
 int launch_sync(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int first,
                 double* out_pos, double* out_vel, double* out_force, double* epart,
                 uint32_t* err, void* stream);

@@ -19,8 +19,8 @@ MD_ECAPACITY, MD_EUNSTABLE, MD_ENOTFOUND, MD_EBUSY, MD_EWATCHDOG = -5, -6, -7, -
 MD_FP64, MD_FP32_FORCE = 0, 1
 OPT_ENERGY_EVERY, OPT_CLAIM_ORDER, OPT_ORDER_SEED, OPT_MIGRATION_LOG = 1, 2, 3, 4
 OPT_CHUNK_CELLS, OPT_COUNT_PAIRS, OPT_WATCHDOG_MS, OPT_GRID = 5, 6, 7, 8
-OPT_FAIL_AT_STEP, OPT_MAX_STEPS_PER_LAUNCH = 9, 10
-ORDER_SWEEP, ORDER_PHASED, ORDER_DESCENDING, ORDER_RANDOM = 0, 1, 2, 3
+OPT_FAIL_AT_STEP, OPT_MAX_STEPS_PER_LAUNCH, OPT_TRACE = 9, 10, 11
+ORDER_SWEEP, ORDER_PHASED, ORDER_DESCENDING, ORDER_RANDOM, ORDER_DATAFLOW = 0, 1, 2, 3, 4
 SERVER_FAKE_EXECUTOR = 1
 
 
@@ -34,6 +34,17 @@ class md_stats(C.Structure):
         ("last_launches", C.c_int32), ("persistent_grid", C.c_int32),
         ("chunks_per_slice", C.c_int32), ("precision", C.c_int32), ("poisoned", C.c_int32),
     ]
+
+
+class md_trace_rec(C.Structure):
+    _fields_ = [("k", C.c_uint32), ("slice", C.c_uint32), ("chunk", C.c_uint32), ("phase", C.c_uint32),
+                ("hw_id", C.c_uint32), ("launch", C.c_uint32),
+                ("t_claim", C.c_uint64), ("t_ready", C.c_uint64), ("t_done", C.c_uint64)]
+
+
+TRACE_DTYPE = np.dtype([("k", "<u4"), ("slice", "<u4"), ("chunk", "<u4"), ("phase", "<u4"),
+                        ("hw_id", "<u4"), ("launch", "<u4"),
+                        ("t_claim", "<u8"), ("t_ready", "<u8"), ("t_done", "<u8")])
 
 
 class md_run_desc(C.Structure):
@@ -68,6 +79,7 @@ _SIGS = {
     "md_get_energy_log": ([C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "md_get_migration_log": ([C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
     "md_get_stats": ([C.c_void_p, C.POINTER(md_stats)], C.c_int),
+    "md_get_trace": ([C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
     "md_set_option": ([C.c_void_p, C.c_int, C.c_int64], C.c_int),
     "md_set_stream": ([C.c_void_p, C.c_void_p], C.c_int),
     "md_free": ([C.c_void_p], None),
@@ -210,6 +222,15 @@ class Sim:
         _check(lib().md_get_migration_log(self._h, steps.value, log.ctypes.data_as(C.POINTER(C.c_int32)),
                                           C.byref(steps)), "md_get_migration_log")
         return log[: steps.value]
+
+    def trace(self):
+        """(records as a numpy structured array, device clock rate in Hz)."""
+        cnt, hz = C.c_int64(), C.c_double()
+        _check(lib().md_get_trace(self._h, 0, None, C.byref(cnt), C.byref(hz)), "md_get_trace")
+        rec = np.zeros(cnt.value, TRACE_DTYPE)
+        _check(lib().md_get_trace(self._h, cnt.value, rec.ctypes.data_as(C.c_void_p), C.byref(cnt),
+                                  C.byref(hz)), "md_get_trace")
+        return rec, hz.value
 
     def stats(self) -> md_stats:
         st = md_stats()
