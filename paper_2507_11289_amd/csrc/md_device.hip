@@ -110,34 +110,51 @@ __device__ __forceinline__ double recip64(double x) {
 }
 
 // ---------------------------------------------------------------------------
-// per-wave LDS scratch
+// Block staging.  A workgroup works on up to BZ consecutive cells of one z-column
+// (one cell per wave).  Their 27-cell neighbourhoods form a 3 x 3 x (nb + 2) block of
+// cells, staged once in LDS in layer-major order (z layer, then dx, then dy), so the
+// 27 neighbours of the cell of wave w are the contiguous entries of layers w .. w+2.
 // ---------------------------------------------------------------------------
-struct ScratchBase {
-  int nb_cell[28];            // global cell of neighbour m = (ox+1)*9 + (oy+1)*3 + (oz+1)
-  uint16_t tag[MAXCAND];      // flat candidate index -> (m << 6) | slot
+constexpr int BZ = WAVES;               // cells per block, one per wave
+constexpr int BLAYERS = BZ + 2;         // staged z layers
+constexpr int BCELLS = 9 * BLAYERS;     // staged cells
+constexpr int CAPB = 27 * CELL_CAP;     // staged atoms at most (one full neighbourhood)
+
+struct BlockHdr {
+  int nb_cell[BCELLS];     // global cell of staged cell m
+  int cnt[BCELLS];         // atoms of staged cell m
+  int pre[BCELLS + 1];     // first staged entry of cell m
+  int nb;                  // cells of this block (after the capacity check)
+  int wrap_col;            // the column touches a periodic boundary in x or y
+  int wrap_layer[BLAYERS]; // z layer is a periodic image
 };
-template <int PREC> struct Scratch;
-template <> struct Scratch<1> : ScratchBase {  // FP32 pair math on cell-relative positions
+
+template <int PREC> struct BlockLDS;
+template <> struct BlockLDS<1> {  // FP32: positions relative to the block origin + tag
+  BlockHdr h;
   union {
-    float4 q[TILE];
-    double red[64 * 6];
+    float4 q[CAPB];
+    double red[WAVES][64 * 6];
   };
 };
-template <> struct Scratch<0> : ScratchBase {  // FP64 pair math on raw positions
+template <> struct BlockLDS<0> {  // FP64: raw positions + tag
+  BlockHdr h;
   union {
     struct {
-      double x[TILE], y[TILE], z[TILE];
+      double x[CAPB], y[CAPB], z[CAPB];
     } t;
-    double red[64 * 6];
+    double red[WAVES][64 * 6];
   };
+  uint16_t tag[CAPB];
 };
 
 struct ForceOut {
   double fx, fy, fz;  // force on the lane's atom (lanes < n)
   double uh, wh;      // half sums of pair energy / pair virial
   unsigned pc;        // in-range partners (count mode)
-  int n;              // atoms in the cell (uniform)
-  int total;          // candidates in the 27 cells, self included (uniform)
+  int n;              // atoms in the cell (uniform per wave)
+  int total;          // candidates in the 27 cells, self included (uniform per wave)
+  int c;              // global cell of the wave (-1: no cell in this block)
 };
 
 // Partial sums of one i-atom held by one lane.
@@ -145,38 +162,41 @@ template <class R> struct Acc {
   R fx, fy, fz;
   double u, w;
   unsigned pc;
-  bool band;  // a pair fell in the FP32 guard band and still has to be decided exactly
 };
 
 template <class R> __device__ __forceinline__ void acc_init(Acc<R>& a) {
   a.fx = a.fy = a.fz = (R)0;
   a.u = a.w = 0.0;
   a.pc = 0;
-  a.band = false;
+}
+
+// LJ pair-force factor F_abs = 24 (2 r^-12 - r^-6) / r^2 = ir2 ir6 (48 ir6 - 24).
+template <class R> __device__ __forceinline__ R force_factor(R ir2, R ir6) {
+  return (ir6 * (ir6 * (R)48 - (R)24)) * ir2;
 }
 
 // FP32 pair for one i-atom against one staged candidate (Algorithm 1 loop body).
 // In range for certain when 0 < r2 <= rc2_lo (r2 == 0 only for the atom itself);
-// pairs with rc2_lo < r2 <= rc2_hi are marked and decided again in FP64 later.
+// pairs with rc2_lo < r2 <= rc2_hi go into the wave mask `band` and are decided again
+// in FP64 afterwards.
 template <bool ENERGY, bool COUNT>
 __device__ __forceinline__ void pair32(float qx, float qy, float qz, const float4& q, unsigned lo_bits,
-                                       unsigned hi_bits, float ucf, Acc<float>& a) {
+                                       unsigned hi_bits, float ucf, Acc<float>& a, unsigned long long& band) {
   const float dx = qx - q.x, dy = qy - q.y, dz = qz - q.z;
   const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
   const unsigned rb = __float_as_uint(r2) - 1u;
   const bool in = rb < lo_bits;
-  a.band |= (rb < hi_bits) & !in;
+  band |= __ballot(rb < hi_bits) & ~__ballot(in);
   const float ir2 = __builtin_amdgcn_rcpf(r2);
   const float ir6 = ir2 * ir2 * ir2;
-  const float t = fmaf(2.0f, ir6, -1.0f);
-  float fr = 24.0f * ir2 * ir6 * t;
+  float fr = force_factor(ir2, ir6);
   fr = in ? fr : 0.0f;
   a.fx = fmaf(fr, dx, a.fx);
   a.fy = fmaf(fr, dy, a.fy);
   a.fz = fmaf(fr, dz, a.fz);
   if (ENERGY) {
     a.u += in ? (double)(4.0f * ir6 * (ir6 - 1.0f) - ucf) : 0.0;
-    a.w += in ? (double)(24.0f * ir6 * t) : 0.0;
+    a.w += in ? (double)(24.0f * ir6 * fmaf(2.0f, ir6, -1.0f)) : 0.0;
   }
   if (COUNT) a.pc += in ? 1u : 0u;
 }
@@ -186,14 +206,13 @@ template <bool ENERGY, bool COUNT>
 __device__ __forceinline__ void pair32_add(float dx, float dy, float dz, float r2, float ucf, Acc<float>& a) {
   const float ir2 = __builtin_amdgcn_rcpf(r2);
   const float ir6 = ir2 * ir2 * ir2;
-  const float t = fmaf(2.0f, ir6, -1.0f);
-  const float fr = 24.0f * ir2 * ir6 * t;
+  const float fr = force_factor(ir2, ir6);
   a.fx = fmaf(fr, dx, a.fx);
   a.fy = fmaf(fr, dy, a.fy);
   a.fz = fmaf(fr, dz, a.fz);
   if (ENERGY) {
     a.u += (double)(4.0f * ir6 * (ir6 - 1.0f) - ucf);
-    a.w += (double)(24.0f * ir6 * t);
+    a.w += (double)(24.0f * ir6 * fmaf(2.0f, ir6, -1.0f));
   }
   if (COUNT) a.pc += 1u;
 }
@@ -212,174 +231,180 @@ __device__ __forceinline__ void pair64(const DGeom& g, double xi, double yi, dou
   const bool in = (r2 <= g.rc2) & (r2 > 0.0);
   const double ir2 = recip64(r2);
   const double ir6 = ir2 * ir2 * ir2;
-  const double t = fma(2.0, ir6, -1.0);
-  double fr = 24.0 * ir2 * ir6 * t;
+  double fr = force_factor(ir2, ir6);
   fr = in ? fr : 0.0;
   a.fx = fma(fr, dx, a.fx);
   a.fy = fma(fr, dy, a.fy);
   a.fz = fma(fr, dz, a.fz);
   if (ENERGY) {
     a.u += in ? 4.0 * ir6 * (ir6 - 1.0) - g.uc : 0.0;
-    a.w += in ? 24.0 * ir6 * t : 0.0;
+    a.w += in ? 24.0 * ir6 * fma(2.0, ir6, -1.0) : 0.0;
   }
   if (COUNT) a.pc += in ? 1u : 0u;
 }
 
-// ---------------------------------------------------------------------------
-// Pair forces of every atom of cell c (Algorithm 1, first loop; kernel md_v3a).
-//
-// The 27 neighbour cells are flattened into one candidate list (tag table in LDS)
-// and staged tile by tile into LDS.  Each lane holds two atoms of the cell (a and
-// a + P, P = ceil(n/2)) and one of G candidate groups; lane (a, grp) visits
-// candidates grp, grp + G, ... so that one LDS read serves two pairs.  Group partials
-// are added in group order, so every atom's sum has a fixed order.
-// ---------------------------------------------------------------------------
+// Stage the block of the column (gx, gy) whose cells start at z0 (at most nb_max of
+// them, all in the column); returns the cells actually taken (capacity may shorten the
+// block).  Whole workgroup; ends with a barrier.
+template <int PREC>
+__device__ int stage_block(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int gx, int gy,
+                           int z0, int nb_max, BlockLDS<PREC>& L) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (tid < 64) {
+    // wave 0: neighbour cells, counts, prefix, capacity
+    const int m = tid;
+    const int lay = m / 9, r = m % 9;
+    int cnt = 0, nc = 0;
+    if (m < BCELLS && lay < nb_max + 2) {
+      int nx = gx + r / 3 - 1, ny = gy + r % 3 - 1, nz = z0 - 1 + lay;
+      nx += nx < 0 ? g.G[0] : (nx >= g.G[0] ? -g.G[0] : 0);
+      ny += ny < 0 ? g.G[1] : (ny >= g.G[1] ? -g.G[1] : 0);
+      nz += nz < 0 ? g.G[2] : (nz >= g.G[2] ? -g.G[2] : 0);
+      nc = global_cell(g, nx, ny, nz);
+      cnt = (int)ncnt[nc];
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off);
+      if (m >= off) incl += v;
+    }
+    if (m < BCELLS) {
+      L.h.nb_cell[m] = nc;
+      L.h.cnt[m] = cnt;
+      L.h.pre[m] = incl - cnt;
+    }
+    if (m == BCELLS - 1) L.h.pre[BCELLS] = incl;
+    // largest nb with its 9 (nb + 2) cells within capacity (nb = 1 always fits)
+    int nb = nb_max;
+    while (nb > 1 && __shfl(incl, 9 * (nb + 2) - 1) > CAPB) nb--;
+    if (m == 0) {
+      L.h.nb = nb;
+      L.h.wrap_col = gx == 0 || gx == g.G[0] - 1 || gy == 0 || gy == g.G[1] - 1;
+    }
+    if (m < BLAYERS) {
+      const int nz = z0 - 1 + m;
+      L.h.wrap_layer[m] = nz < 0 || nz >= g.G[2];
+    }
+  }
+  __syncthreads();
+  const int nb = L.h.nb;
+  // stage: 4 threads per staged cell, slots sub, sub + 4, ...
+  const int ms = tid >> 2, sub = tid & 3;
+  // FP32 origin: the column corner at the start of z0's aligned group of BZ cells, so a
+  // pair's FP32 arithmetic depends on the cell only, not on how cells form blocks
+  const double ox = gx * g.l[0], oy = gy * g.l[1], oz = (z0 - z0 % BZ) * g.l[2];
+  for (int mb = 0; mb < 9 * (nb + 2); mb += WG / 4) {
+    const int m = mb + ms;
+    if (m >= 9 * (nb + 2)) break;
+    const int n = L.h.cnt[m];
+    if (n == 0) continue;
+    const double* jb = cblk(cells, L.h.nb_cell[m]);
+    const int p = L.h.pre[m];
+    double shx = 0.0, shy = 0.0, shz = 0.0;
+    if constexpr (PREC == 1) {
+      const int lay = m / 9, r = m % 9;
+      const int nx = gx + r / 3 - 1, ny = gy + r % 3 - 1, nz = z0 - 1 + lay;
+      shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
+      shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
+      shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
+    }
+    for (int k = sub; k < n; k += 4) {
+      const double x = jb[k], y = jb[CELL_CAP + k], z = jb[2 * CELL_CAP + k];
+      if constexpr (PREC == 1) {
+        L.q[p + k] = make_float4((float)((x + shx) - ox), (float)((y + shy) - oy), (float)((z + shz) - oz),
+                                 __uint_as_float(((unsigned)m << 6) | (unsigned)k));
+      } else {
+        L.t.x[p + k] = x;
+        L.t.y[p + k] = y;
+        L.t.z[p + k] = z;
+        L.tag[p + k] = (uint16_t)((m << 6) | k);
+      }
+    }
+  }
+  __syncthreads();
+  return nb;
+}
+
+// Pair forces of every atom of the cell of this wave in the staged block
+// (Algorithm 1, first loop; kernel md_v3a).  Each lane holds two atoms of the cell
+// (a and a + P, P = ceil(n/2)) and one of G candidate groups; lane (a, grp) visits
+// candidates grp, grp + G, ... of the cell's 27-cell window, so one LDS read serves two
+// pairs.  Group partials are added in group order: every atom's sum has a fixed order.
+// Whole workgroup (contains barriers); waves without a cell only take part in those.
 template <int PREC, bool ENERGY, bool COUNT>
-__device__ void cell_force(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int c,
-                           Scratch<PREC>& ws, ForceOut& o) {
+__device__ void block_force(const DGeom& g, const unsigned char* cells, int gx, int gy, int z0,
+                            BlockLDS<PREC>& L, ForceOut& o) {
   using R = typename std::conditional<PREC == 1, float, double>::type;
   const int lane = __lane_id();
-  const int n_i = (int)ncnt[c];
+  const int w = threadIdx.x >> 6;
+  const int nb = L.h.nb;
+  const bool mine = w < nb;
+  const int ci = 9 * (w + 1) + 4;  // staged index of the wave's own cell
+  const int n_i = mine ? L.h.cnt[ci] : 0;
+  const int beg = mine ? L.h.pre[9 * w] : 0;
+  const int total = mine ? L.h.pre[9 * (w + 3)] - beg : 0;
   o.n = n_i;
+  o.total = total;
+  o.c = mine ? L.h.nb_cell[ci] : -1;
   o.fx = o.fy = o.fz = 0.0;
   o.uh = o.wh = 0.0;
   o.pc = 0;
-  o.total = 0;
-  if (n_i == 0) return;
-
-  int gx, gy, gz;
-  cell_xyz(g, c, gx, gy, gz);
-
-  // neighbour table: lane m < 27 handles neighbour m
-  int cnt = 0, nc = 0;
-  bool wrapped = false;
-  if (lane < 27) {
-    int nx = gx + lane / 9 - 1, ny = gy + (lane / 3) % 3 - 1, nz = gz + lane % 3 - 1;
-    wrapped = nx < 0 || nx >= g.G[0] || ny < 0 || ny >= g.G[1] || nz < 0 || nz >= g.G[2];
-    nx += nx < 0 ? g.G[0] : (nx >= g.G[0] ? -g.G[0] : 0);
-    ny += ny < 0 ? g.G[1] : (ny >= g.G[1] ? -g.G[1] : 0);
-    nz += nz < 0 ? g.G[2] : (nz >= g.G[2] ? -g.G[2] : 0);
-    nc = global_cell(g, nx, ny, nz);
-    cnt = (int)ncnt[nc];
-  }
-  int incl = cnt, mx = cnt;
-#pragma unroll
-  for (int off = 1; off < 32; off <<= 1) {
-    const int v = __shfl_up(incl, off);
-    if (lane >= off) incl += v;
-    mx = max(mx, __shfl_xor(mx, off));
-  }
-  const int total = __shfl(incl, 26);
-  const bool any_wrap = __ballot(wrapped) != 0ull;
-  const int excl = incl - cnt;
-  wave_sync();
-  if (lane < 27) ws.nb_cell[lane] = nc;
-  for (int k = 0; k < mx; k++)
-    if (lane < 27 && k < cnt) ws.tag[excl + k] = (uint16_t)((lane << 6) | k);
-  wave_sync();
-  o.total = total;
-
-  // lane layout: atoms a and a + P, candidate group grp of G
-  const int P = (n_i + 1) >> 1;
-  int G = 64 / P;
-  if (G > 16) G = 16;
-  const int ia = lane % P;
-  const int grp = lane / P;
-  const bool act = grp < G;
-  const int ib_ = ia + P;
-  const bool has_b = ib_ < n_i;
-  const double* iblk = cblk(cells, c);
 
   Acc<R> A, B;
   acc_init(A);
   acc_init(B);
-
-  // cell origin (FP32 coordinates are taken relative to it)
-  const double ox = gx * g.l[0], oy = gy * g.l[1], oz = gz * g.l[2];
-  R aix, aiy, aiz, bix, biy, biz;
-  if constexpr (PREC == 1) {
-    aix = (float)(iblk[ia] - ox);
-    aiy = (float)(iblk[CELL_CAP + ia] - oy);
-    aiz = (float)(iblk[2 * CELL_CAP + ia] - oz);
-    // a missing second atom sits far away and never interacts
-    bix = has_b ? (float)(iblk[ib_] - ox) : 1e30f;
-    biy = has_b ? (float)(iblk[CELL_CAP + ib_] - oy) : 1e30f;
-    biz = has_b ? (float)(iblk[2 * CELL_CAP + ib_] - oz) : 1e30f;
-  } else {
-    aix = iblk[ia];
-    aiy = iblk[CELL_CAP + ia];
-    aiz = iblk[2 * CELL_CAP + ia];
-    bix = has_b ? iblk[ib_] : 1e300;
-    biy = has_b ? iblk[CELL_CAP + ib_] : 1e300;
-    biz = has_b ? iblk[2 * CELL_CAP + ib_] : 1e300;
-  }
-  const unsigned lo_bits = __float_as_uint(g.rc2_lo_f), hi_bits = __float_as_uint(g.rc2_hi_f);
-
-  for (int tb = 0; tb < total; tb += TILE) {
-    const int tn = min(TILE, total - tb);
-    wave_sync();
-    // stage the tile: all loads of a lane are issued before the conversions
-    double sx[TILE / 64], sy[TILE / 64], sz[TILE / 64];
-    int sm[TILE / 64];
-#pragma unroll
-    for (int u = 0; u < TILE / 64; u++) {
-      const int e = lane + 64 * u;
-      sm[u] = 0;
-      sx[u] = sy[u] = sz[u] = 0.0;
-      if (e < tn) {
-        const unsigned tg = ws.tag[tb + e];
-        const int m = (int)(tg >> 6), k = (int)(tg & 63u);
-        const double* jb = cblk(cells, ws.nb_cell[m]);
-        sx[u] = jb[k];
-        sy[u] = jb[CELL_CAP + k];
-        sz[u] = jb[2 * CELL_CAP + k];
-        sm[u] = m;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < TILE / 64; u++) {
-      const int e = lane + 64 * u;
-      if (e < tn) {
-        if constexpr (PREC == 1) {
-          const int m = sm[u];
-          const int nx = gx + m / 9 - 1, ny = gy + (m / 3) % 3 - 1, nz = gz + m % 3 - 1;
-          const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
-          const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
-          const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
-          ws.q[e] = make_float4((float)((sx[u] + shx) - ox), (float)((sy[u] + shy) - oy),
-                                (float)((sz[u] + shz) - oz), 0.0f);
-        } else {
-          ws.t.x[e] = sx[u];
-          ws.t.y[e] = sy[u];
-          ws.t.z[e] = sz[u];
-        }
-      }
-    }
-    wave_sync();
-    const int f0 = act ? grp : tn;
+  int P = 1, G = 1, ia = 0, ib_ = 0;
+  if (n_i > 0) {
+    P = (n_i + 1) >> 1;
+    G = 64 / P;
+    if (G > 16) G = 16;
+    ia = lane % P;
+    const int grp = lane / P;
+    ib_ = ia + P;
+    const bool has_b = ib_ < n_i;
+    const int f0 = grp < G ? beg + grp : beg + total;
+    const int fe = beg + total;
+    const int si = L.h.pre[ci];  // own atoms in the staged list
+    const unsigned lo_bits = __float_as_uint(g.rc2_lo_f), hi_bits = __float_as_uint(g.rc2_hi_f);
     if constexpr (PREC == 1) {
-#pragma unroll 2
-      for (int f = f0; f < tn; f += G) {
-        const float4 q = ws.q[f];
-        pair32<ENERGY, COUNT>(aix, aiy, aiz, q, lo_bits, hi_bits, g.uc_f, A);
-        pair32<ENERGY, COUNT>(bix, biy, biz, q, lo_bits, hi_bits, g.uc_f, B);
+      const float4 qa = L.q[si + ia];
+      // a missing second atom sits far away and never interacts
+      const float4 qb = has_b ? L.q[si + ib_] : make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+      unsigned long long band_a = 0ull, band_b = 0ull;
+      int f = f0;
+      // two candidates per iteration (four pairs), then the remainder
+      for (; f + G < fe; f += 2 * G) {
+        const float4 q0 = L.q[f];
+        const float4 q1 = L.q[f + G];
+        pair32<ENERGY, COUNT>(qa.x, qa.y, qa.z, q0, lo_bits, hi_bits, g.uc_f, A, band_a);
+        pair32<ENERGY, COUNT>(qb.x, qb.y, qb.z, q0, lo_bits, hi_bits, g.uc_f, B, band_b);
+        pair32<ENERGY, COUNT>(qa.x, qa.y, qa.z, q1, lo_bits, hi_bits, g.uc_f, A, band_a);
+        pair32<ENERGY, COUNT>(qb.x, qb.y, qb.z, q1, lo_bits, hi_bits, g.uc_f, B, band_b);
+      }
+      if (f < fe) {
+        const float4 q0 = L.q[f];
+        pair32<ENERGY, COUNT>(qa.x, qa.y, qa.z, q0, lo_bits, hi_bits, g.uc_f, A, band_a);
+        pair32<ENERGY, COUNT>(qb.x, qb.y, qb.z, q0, lo_bits, hi_bits, g.uc_f, B, band_b);
       }
       // guard band: decide those pairs in FP64 exactly as the FP64 path would
-      if (__ballot(A.band || B.band)) {
+      if (band_a | band_b) {
+        const double* iblk = cblk(cells, o.c);
         for (int h = 0; h < 2; h++) {
           Acc<float>& X = h == 0 ? A : B;
-          if (!X.band) continue;
+          if (!(((h == 0 ? band_a : band_b) >> lane) & 1ull)) continue;
           const int a = h == 0 ? ia : ib_;
-          const float qx = h == 0 ? aix : bix, qy = h == 0 ? aiy : biy, qz = h == 0 ? aiz : biz;
+          const float4 qi = h == 0 ? qa : qb;
           const double xi = iblk[a], yi = iblk[CELL_CAP + a], zi = iblk[2 * CELL_CAP + a];
-          for (int f = f0; f < tn; f += G) {
-            const float4 q = ws.q[f];
-            const float dx = qx - q.x, dy = qy - q.y, dz = qz - q.z;
+          for (int f = f0; f < fe; f += G) {
+            const float4 q = L.q[f];
+            const float dx = qi.x - q.x, dy = qi.y - q.y, dz = qi.z - q.z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             const unsigned rb = __float_as_uint(r2) - 1u;
             if (rb >= lo_bits && rb < hi_bits) {
-              const unsigned tg = ws.tag[tb + f];
-              const double* jb = cblk(cells, ws.nb_cell[tg >> 6]);
+              const unsigned tg = __float_as_uint(q.w);
+              const double* jb = cblk(cells, L.h.nb_cell[tg >> 6]);
               const int k = (int)(tg & 63u);
               const double ex = min_img(__dsub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
               const double ey = min_img(__dsub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
@@ -387,69 +412,96 @@ __device__ void cell_force(const DGeom& g, const unsigned char* cells, const uin
               if (r2_exact(ex, ey, ez) <= g.rc2) pair32_add<ENERGY, COUNT>(dx, dy, dz, r2, g.uc_f, X);
             }
           }
-          X.band = false;
         }
       }
     } else {
-      if (!any_wrap) {
+      const double ax = L.t.x[si + ia], ay = L.t.y[si + ia], az = L.t.z[si + ia];
+      const double bx = has_b ? L.t.x[si + ib_] : 1e300, by = has_b ? L.t.y[si + ib_] : 1e300,
+                   bz = has_b ? L.t.z[si + ib_] : 1e300;
+      const bool wrap = L.h.wrap_col || L.h.wrap_layer[w] || L.h.wrap_layer[w + 2];
+      if (!wrap) {
+        // no periodic neighbour: the raw difference is the minimum image of every pair
+        // that can be in range
 #pragma unroll 2
-        for (int f = f0; f < tn; f += G) {
-          const double xj = ws.t.x[f], yj = ws.t.y[f], zj = ws.t.z[f];
-          pair64<ENERGY, COUNT, false>(g, aix, aiy, aiz, xj, yj, zj, A);
-          pair64<ENERGY, COUNT, false>(g, bix, biy, biz, xj, yj, zj, B);
+        for (int f = f0; f < fe; f += G) {
+          const double xj = L.t.x[f], yj = L.t.y[f], zj = L.t.z[f];
+          pair64<ENERGY, COUNT, false>(g, ax, ay, az, xj, yj, zj, A);
+          pair64<ENERGY, COUNT, false>(g, bx, by, bz, xj, yj, zj, B);
         }
       } else {
-        for (int f = f0; f < tn; f += G) {
-          const double xj = ws.t.x[f], yj = ws.t.y[f], zj = ws.t.z[f];
-          pair64<ENERGY, COUNT, true>(g, aix, aiy, aiz, xj, yj, zj, A);
-          pair64<ENERGY, COUNT, true>(g, bix, biy, biz, xj, yj, zj, B);
+        for (int f = f0; f < fe; f += G) {
+          const double xj = L.t.x[f], yj = L.t.y[f], zj = L.t.z[f];
+          pair64<ENERGY, COUNT, true>(g, ax, ay, az, xj, yj, zj, A);
+          pair64<ENERGY, COUNT, true>(g, bx, by, bz, xj, yj, zj, B);
         }
       }
     }
   }
-
-  // add the group partials of each atom in group order (first the a atoms, then the b)
-  double sa[6] = {0, 0, 0, 0, 0, 0}, sb[6] = {0, 0, 0, 0, 0, 0};
-  double* red = ws.red;
-  for (int h = 0; h < 2; h++) {
-    const Acc<R>& X = h == 0 ? A : B;
-    wave_sync();
-    red[lane * 6 + 0] = (double)X.fx;
-    red[lane * 6 + 1] = (double)X.fy;
-    red[lane * 6 + 2] = (double)X.fz;
-    red[lane * 6 + 3] = X.u;
-    red[lane * 6 + 4] = X.w;
-    red[lane * 6 + 5] = (double)X.pc;
-    wave_sync();
-    if (lane < P) {
-      double* s = h == 0 ? sa : sb;
-      for (int q = 0; q < G; q++) {
-        const double* r = red + (lane + q * P) * 6;
+  // every wave is done with the staged positions; the same LDS now holds the partials
+  __syncthreads();
+  if (n_i > 0) {
+    double sa[6] = {0, 0, 0, 0, 0, 0}, sb[6] = {0, 0, 0, 0, 0, 0};
+    double* red = L.red[w];
+    for (int h = 0; h < 2; h++) {
+      const Acc<R>& X = h == 0 ? A : B;
+      wave_sync();
+      red[lane * 6 + 0] = (double)X.fx;
+      red[lane * 6 + 1] = (double)X.fy;
+      red[lane * 6 + 2] = (double)X.fz;
+      red[lane * 6 + 3] = X.u;
+      red[lane * 6 + 4] = X.w;
+      red[lane * 6 + 5] = (double)X.pc;
+      wave_sync();
+      if (lane < P) {
+        double* s = h == 0 ? sa : sb;
+        for (int q = 0; q < G; q++) {
+          const double* r = red + (lane + q * P) * 6;
 #pragma unroll
-        for (int v = 0; v < 6; v++) s[v] += r[v];
+          for (int v = 0; v < 6; v++) s[v] += r[v];
+        }
       }
     }
-  }
-  wave_sync();
-  if (lane < P) {
+    wave_sync();
+    if (lane < P) {
 #pragma unroll
-    for (int v = 0; v < 6; v++) red[lane * 6 + v] = sa[v];
-    if (lane + P < n_i) {
+      for (int v = 0; v < 6; v++) red[lane * 6 + v] = sa[v];
+      if (lane + P < n_i) {
 #pragma unroll
-      for (int v = 0; v < 6; v++) red[(lane + P) * 6 + v] = sb[v];
+        for (int v = 0; v < 6; v++) red[(lane + P) * 6 + v] = sb[v];
+      }
+    }
+    wave_sync();
+    if (lane < n_i) {
+      const double* r = red + lane * 6;
+      o.fx = r[0];
+      o.fy = r[1];
+      o.fz = r[2];
+      o.uh = 0.5 * r[3];
+      o.wh = 0.5 * r[4];
+      o.pc = (unsigned)r[5];
     }
   }
-  wave_sync();
-  if (lane < n_i) {
-    const double* r = red + lane * 6;
-    o.fx = r[0];
-    o.fy = r[1];
-    o.fz = r[2];
-    o.uh = 0.5 * r[3];
-    o.wh = 0.5 * r[4];
-    o.pc = (unsigned)r[5];
+}
+
+// Walk the cells [b, e) of one slice (local indices, z fastest) block by block; fn(o)
+// runs on every wave after each block's forces.  Whole workgroup.
+template <int PREC, bool ENERGY, bool COUNT, class Fn>
+__device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int slice, int b,
+                           int e, BlockLDS<PREC>& L, Fn&& fn) {
+  int x = b;
+  while (x < e) {
+    const int gz = x % g.G[2];
+    const int t = x / g.G[2];
+    const int gy = t % g.G[1];
+    const int gx = slice * g.ncx + t / g.G[1];
+    // blocks stay within the column and within one aligned group of BZ cells
+    const int nb_max = min(min(BZ - gz % BZ, e - x), g.G[2] - gz);
+    const int nb = stage_block<PREC>(g, cells, ncnt, gx, gy, gz, nb_max, L);
+    ForceOut o;
+    block_force<PREC, ENERGY, COUNT>(g, cells, gx, gy, gz, L, o);
+    fn(o);
+    x += nb;
   }
-  wave_sync();
 }
 
 // Per-item accumulators of one wave.
@@ -466,7 +518,7 @@ __device__ __forceinline__ void acc_zero(ItemAcc& a) {
 }
 
 // ---------------------------------------------------------------------------
-// Force + velocity-Verlet + migration of one cell (kernels md_v3a, md_v3aa, md_v3b).
+// Velocity-Verlet + migration of one cell after its forces (kernels md_v3aa, md_v3b).
 // The stored velocity is the half-step velocity v(t - dt/2), or v(t) itself on the
 // first step after a load.  One step of the synchronous form:
 //   v(t) = v(t-dt/2) + (dt/2) F(t);  v(t+dt/2) = v(t) + (dt/2) F(t);
@@ -474,14 +526,14 @@ __device__ __forceinline__ void acc_zero(ItemAcc& a) {
 // stored: the same cell (kept in order), or appended to another cell -- possibly in
 // the left or right neighbour slice.
 // ---------------------------------------------------------------------------
-template <int PREC, bool ENERGY, bool COUNT>
-__device__ void p2_cell(const RunArgs& ra, int c, int src, int first, Scratch<PREC>& ws,
-                        ItemAcc& acc, uint32_t* abort_flag) {
+template <bool ENERGY, bool COUNT>
+__device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first, ItemAcc& acc,
+                        uint32_t* abort_flag) {
   const DGeom& g = ra.g;
-  ForceOut o;
-  cell_force<PREC, ENERGY, COUNT>(g, ra.cells[src], ra.ncnt[src], c, ws, o);
   const int lane = __lane_id();
   const int dst = src ^ 1;
+  const int c = o.c;
+  if (c < 0) return;
   if (o.n == 0) {
     if (lane == 0) ra.ncnt[dst][c] = 0u;
     return;
@@ -671,18 +723,18 @@ __device__ bool wait_counters(const LaunchArgs& la, const uint32_t* cnt, int S, 
 }
 
 template <int PREC, bool ENERGY, bool COUNT>
-__device__ void run_p2_item(const RunArgs& ra, const Item& it, Scratch<PREC>& ws, double (*s_red)[3],
+__device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L, double (*s_red)[3],
                             unsigned long long (*s_cnt)[4], uint32_t* abort_flag) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int src = (ra.par0 + it.k) & 1;
   const int first = (it.k == 0) ? ra.first : 0;
   const int b = (int)((long long)ra.g.cps * it.chunk / ra.nch);
   const int e = (int)((long long)ra.g.cps * (it.chunk + 1) / ra.nch);
-  const int cbase = it.slice * ra.g.cps;
   ItemAcc acc;
   acc_zero(acc);
-  for (int lc = b + wave; lc < e; lc += WAVES)
-    p2_cell<PREC, ENERGY, COUNT>(ra, cbase + lc, src, first, ws, acc, abort_flag);
+  for_blocks<PREC, ENERGY, COUNT>(ra.g, ra.cells[src], ra.ncnt[src], it.slice, b, e, L, [&](const ForceOut& o) {
+    p2_tail<ENERGY, COUNT>(ra, o, src, first, acc, abort_flag);
+  });
   // wave reductions (fixed butterfly), then waves in order
   double u = acc.u, w = acc.w, k = acc.k;
   unsigned long long cc = acc.cand, pc = acc.inr;
@@ -747,7 +799,7 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, Scratch<PREC>& ws
 }
 
 template <int PREC, bool FULL>
-__device__ void run_item(const RunArgs& ra, const Item& it, Scratch<PREC>& ws, double (*s_red)[3],
+__device__ void run_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& ws, double (*s_red)[3],
                          unsigned long long (*s_cnt)[4]) {
   const int wave = threadIdx.x >> 6;
   if (it.phase == 0) {
@@ -800,8 +852,8 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
 
 // FULL = false: launches without energy samples or pair counting (fewer registers).
 template <int PREC, bool FULL>
-__global__ __launch_bounds__(WG) void persistent_kernel(LaunchArgs la) {
-  __shared__ Scratch<PREC> ws[WAVES];
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void persistent_kernel(LaunchArgs la) {
+  __shared__ BlockLDS<PREC> ws;
   __shared__ double s_red[WAVES][3];
   __shared__ unsigned long long s_cnt[WAVES][4];
   __shared__ Item s_it;
@@ -886,7 +938,7 @@ __global__ __launch_bounds__(WG) void persistent_kernel(LaunchArgs la) {
     const int ok = s_ok;
     if (ok) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      run_item<PREC, FULL>(ra, it, ws[wave], s_red, s_cnt);
+      run_item<PREC, FULL>(ra, it, ws, s_red, s_cnt);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
@@ -984,17 +1036,18 @@ __global__ __launch_bounds__(WG) void sync_kernel(DGeom g, const unsigned char* 
                                                   const uint32_t* ncnt, int first, double* out_pos,
                                                   double* out_vel, double* out_force, double* epart,
                                                   uint32_t* err) {
-  __shared__ Scratch<PREC> ws[WAVES];
+  __shared__ BlockLDS<PREC> L;
   __shared__ double s_red[WAVES][3];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double u = 0, w = 0, k = 0;
-  const int b = blockIdx.x * SYNC_CELLS;
-  const int e = min(g.ncell, b + SYNC_CELLS);
-  for (int c = b + wave; c < e; c += WAVES) {
-    ForceOut o;
-    cell_force<PREC, true, false>(g, cells, ncnt, c, ws[wave], o);
-    if (lane < o.n) {
-      const double* ib = cblk(cells, c);
+  // SYNC_CELLS consecutive cells of one slice per workgroup
+  const int per_slice = (g.cps + SYNC_CELLS - 1) / SYNC_CELLS;
+  const int slice = blockIdx.x / per_slice;
+  const int b = (blockIdx.x % per_slice) * SYNC_CELLS;
+  const int e = min(g.cps, b + SYNC_CELLS);
+  for_blocks<PREC, true, false>(g, cells, ncnt, slice, b, e, L, [&](const ForceOut& o) {
+    if (o.c >= 0 && lane < o.n) {
+      const double* ib = cblk(cells, o.c);
       const uint32_t id = cids(ib)[lane];
       const double F[3] = {o.fx, o.fy, o.fz};
       double vf[3];
@@ -1011,7 +1064,7 @@ __global__ __launch_bounds__(WG) void sync_kernel(DGeom g, const unsigned char* 
       u += o.uh;
       w += o.wh;
     }
-  }
+  });
   for (int off = 32; off >= 1; off >>= 1) {
     u += __shfl_xor(u, off);
     w += __shfl_xor(w, off);
@@ -1127,7 +1180,7 @@ int launch_persistent(const LaunchArgs& la, int prec, int full, int grid, void* 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int sync_blocks(const DGeom& g) { return (g.ncell + SYNC_CELLS - 1) / SYNC_CELLS; }
+int sync_blocks(const DGeom& g) { return g.S * ((g.cps + SYNC_CELLS - 1) / SYNC_CELLS); }
 
 int launch_sync(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int first,
                 double* out_pos, double* out_vel, double* out_force, double* epart, uint32_t* err,

@@ -1,0 +1,146 @@
+"""GPU parity at the full workload sizes, on sampled atoms the oracle computes one by
+one, and on exact integer properties (binning, candidate and in-range pair counts,
+migration counts) that the oracle evaluates for every atom.
+
+  * 4,194,304-atom LJ fluid (rho 0.8, T 1.0, 64 slices), both precisions;
+  * 8,388,608-atom vapour-liquid slab (512 slices), FP32 forces;
+  * 33,554,432-atom near-triple-point liquid (256 slices, 4:1:1 box): forces of a
+    seeded 1% subsample in both precisions (the precision study).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2507_11289_amd import inputs, md
+
+pytestmark = [pytest.mark.gpu]
+
+TOL = {md.MD_FP64: 1e-12, md.MD_FP32_FORCE: 1e-5}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def subsample(n, frac, seed):
+    """Seeded partial Fisher-Yates choice of round(frac * n) ids (sorted)."""
+    m = max(1, int(round(frac * n)))
+    st = inputs.Stream(seed)
+    u = st.uniform(m)
+    idx = np.arange(n, dtype=np.int64)
+    for k in range(m):
+        j = k + int(u[k] * (n - k))
+        idx[k], idx[j] = idx[j], idx[k]
+    return np.sort(idx[:m])
+
+
+@pytest.fixture(scope="module")
+def fluid4m():
+    say("[gpu-scale] generating lj_fluid_4m")
+    return inputs.lj_fluid_4m()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [md.MD_FP32_FORCE, md.MD_FP64])
+def test_fluid_4m_binning_counts_and_sampled_forces(fluid4m, prec):
+    s = fluid4m
+    g = ref.geometry(s.box, s.slices, s.rc)
+    ids = subsample(s.n, 1e-3, 77)
+    say(f"[gpu-scale] lj_fluid_4m precision={prec}: load, binning, pair counts")
+    with md.Sim(s.box, s.slices, s.rc, s.dt, prec) as sim:
+        sim.load(s.pos, s.vel)
+        _, _, ocell = ref.bin_atoms(g, s.pos)
+        np.testing.assert_array_equal(sim.cells(), ocell)
+        np.testing.assert_array_equal(sim.slice_counts(), np.bincount(ocell // g.cells_per_slice,
+                                                                      minlength=s.slices))
+        pos0, vel0, F0 = sim.state()
+        o = ref.forces_subset(g, s.pos, ids)
+        e = ref.force_error(F0[ids], o["F"], o["scale"])
+        say(f"    t=0 sampled max e_i = {e.max():.3e}")
+        assert e.max() <= TOL[prec]
+        # exact integer pair statistics of the whole system at t = 0
+        sim.set_option(md.OPT_COUNT_PAIRS, 1)
+        sim.set_option(md.OPT_MIGRATION_LOG, 1)
+        sim.step(1)
+        st = sim.stats()
+        full = ref.forces_cells(g, s.pos)
+        assert st.candidates == int(full["cand"].sum())
+        assert st.in_range == int(full["inr"].sum())
+        mig1 = sim.migration_log()
+        sim.set_option(md.OPT_COUNT_PAIRS, 0)
+        sim.step(9)
+        mig = np.concatenate([mig1, sim.migration_log()])
+        pos, vel, F = sim.state()
+    # the GPU's binning of its own positions after 10 steps
+    _, _, ocell10 = ref.bin_atoms(g, pos)
+    # forces at t = 10 from the GPU's own FP64 positions
+    o10 = ref.forces_subset(g, pos, ids)
+    e10 = ref.force_error(F[ids], o10["F"], o10["scale"])
+    say(f"    t=10 sampled max e_i = {e10.max():.3e}")
+    assert e10.max() <= TOL[prec]
+    if prec == md.MD_FP64:
+        # migration counts step by step against the oracle's own 10-step trajectory
+        say("    oracle 10-step trajectory for the migration log")
+        orun = ref.run(g, s.pos, s.vel, s.dt, 10, miglog=True)
+        np.testing.assert_array_equal(mig, orun["miglog"])
+        d = pos - orun["pos"]
+        L = np.array(s.box)
+        d -= L * np.round(d / L)
+        assert np.abs(d).max() < 1e-9
+
+
+@pytest.mark.timeout(900)
+def test_slab_8m_binning_and_sampled_forces():
+    say("[gpu-scale] generating lj_slab_8m")
+    s = inputs.lj_slab_8m()
+    g = ref.geometry(s.box, s.slices, s.rc)
+    prec = md.MD_FP32_FORCE
+    n_l = s.meta["n_liquid"]
+    ids = np.concatenate([subsample(n_l, 2e-4, 91), n_l + subsample(s.n - n_l, 2e-3, 92)])
+    with md.Sim(s.box, s.slices, s.rc, s.dt, prec) as sim:
+        sim.load(s.pos, s.vel)
+        counts = sim.slice_counts()
+        say(f"    atoms per slice: min {counts.min()} max {counts.max()}")
+        assert counts.max() > 20 * max(counts.min(), 1)   # strongly uneven
+        _, _, ocell = ref.bin_atoms(g, s.pos)
+        np.testing.assert_array_equal(sim.cells(), ocell)
+        sim.set_option(md.OPT_MIGRATION_LOG, 1)
+        sim.step(5)
+        pos, vel, F = sim.state()
+        mig = sim.migration_log()
+    o = ref.forces_subset(g, pos, ids)
+    e = ref.force_error(F[ids], o["F"], o["scale"])
+    n_liq_ids = int((ids < n_l).sum())
+    say(f"    t=5 sampled max e_i = {e.max():.3e} (liquid {e[:n_liq_ids].max():.3e}, "
+        f"vapour {e[n_liq_ids:].max() if len(ids) > n_liq_ids else 0:.3e})")
+    assert e.max() <= TOL[prec]
+    _, _, ocell5 = ref.bin_atoms(g, pos)
+    # migrations happen at every boundary region (liquid and vapour)
+    assert mig.sum() > 0
+
+
+@pytest.mark.timeout(1200)
+def test_liquid_32m_subsample_precision_study():
+    say("[gpu-scale] generating lj_liquid_32m")
+    s = inputs.lj_liquid_32m()
+    g = ref.geometry(s.box, s.slices, s.rc)
+    ids = subsample(s.n, 0.01, 2507)          # the seeded 1% subsample
+    say(f"    {len(ids)} sampled atoms; oracle subset forces at t=0")
+    o = ref.forces_subset(g, s.pos, ids)
+    for prec in (md.MD_FP32_FORCE, md.MD_FP64):
+        say(f"[gpu-scale] lj_liquid_32m precision={prec}")
+        with md.Sim(s.box, s.slices, s.rc, s.dt, prec) as sim:
+            sim.load(s.pos, s.vel)
+            _, _, F = sim.state()
+            e = ref.force_error(F[ids], o["F"], o["scale"])
+            say(f"    t=0 1% subsample: max e_i {e.max():.3e}, median {np.median(e):.3e}")
+            assert e.max() <= TOL[prec]
+            sim.step(10)
+            pos, _, F10 = sim.state()
+        o10 = ref.forces_subset(g, pos, ids)
+        e10 = ref.force_error(F10[ids], o10["F"], o10["scale"])
+        say(f"    t=10 1% subsample: max e_i {e10.max():.3e}")
+        assert e10.max() <= TOL[prec]

@@ -1,0 +1,141 @@
+"""Serving on the GPU: independent runs admitted by device footprint, packed into
+shared persistent launches; every result must be the same alone and in the mix
+(bitwise: each run's arithmetic depends only on its own state)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2507_11289_amd import inputs, md
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def wait_all(sv, tickets, timeout=120):
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        assert time.time() - t0 < timeout, "served runs did not finish"
+        for t in tickets:
+            if t in done:
+                continue
+            rc, r = sv.poll(t)
+            if rc != md.MD_PENDING:
+                done[t] = (rc, r)
+        time.sleep(0.001)
+    return done
+
+
+def requests(k, seed=5):
+    out = []
+    reqs = inputs.served_ensemble(count=k, seed=seed)
+    for r in reqs:
+        r.steps = 40 + (r.index * 37) % 60
+        r.n = min(r.n, 30000)
+        out.append((r, r.system()))
+    return out
+
+
+@pytest.mark.timeout(300)
+def test_alone_equals_mixed_bitwise():
+    runs = requests(12)
+    say(f"[gpu-serve] {len(runs)} runs alone")
+    alone = {}
+    sv = md.Server(8 << 30, 1, quantum_steps=16)
+    try:
+        for r, s in runs:
+            t = sv.submit(s.box, s.slices, s.pos, s.vel, r.steps, precision=md.MD_FP32_FORCE,
+                          energy_every=10, tag=r.index, keep_state=True)
+            (rc, res), = wait_all(sv, [t]).values()
+            assert rc == md.MD_OK, md.md_strerror(rc)
+            alone[r.index] = (res.U1, res.K1, res.W1, sv.fetch_state(t, s.n))
+    finally:
+        sv.close()
+    say("[gpu-serve] the same runs in one mix")
+    sv = md.Server(8 << 30, 16, quantum_steps=7)
+    try:
+        tickets = {}
+        for r, s in runs:
+            tickets[sv.submit(s.box, s.slices, s.pos, s.vel, r.steps, precision=md.MD_FP32_FORCE,
+                              energy_every=10, tag=r.index, keep_state=True)] = (r, s)
+        done = wait_all(sv, list(tickets))
+        for t, (rc, res) in done.items():
+            r, s = tickets[t]
+            assert rc == md.MD_OK
+            U1, K1, W1, (p, v) = alone[r.index]
+            assert (res.U1, res.K1, res.W1) == (U1, K1, W1)
+            p2, v2 = sv.fetch_state(t, s.n)
+            np.testing.assert_array_equal(p2, p)
+            np.testing.assert_array_equal(v2, v)
+        assert sv.stats()["launches"] < sum(r.steps for r, _ in runs) / 7
+    finally:
+        sv.close()
+
+
+@pytest.mark.timeout(300)
+def test_served_run_matches_a_plain_simulation_and_the_oracle():
+    (r, s), = requests(1, seed=9)
+    say(f"[gpu-serve] one run n={s.n} steps={r.steps} vs md_step and the oracle")
+    sv = md.Server(4 << 30, 4)
+    try:
+        t = sv.submit(s.box, s.slices, s.pos, s.vel, r.steps, precision=md.MD_FP64, keep_state=True)
+        (rc, res), = wait_all(sv, [t]).values()
+        assert rc == md.MD_OK
+        p, v = sv.fetch_state(t, s.n)
+    finally:
+        sv.close()
+    with md.Sim(s.box, s.slices, s.rc, s.dt, md.MD_FP64) as sim:
+        sim.load(s.pos, s.vel)
+        U0, K0, W0 = sim.energy_virial()
+        sim.step(r.steps)
+        p2, v2, _ = sim.state()
+        U1, K1, W1 = sim.energy_virial()
+    np.testing.assert_array_equal(p, p2)
+    np.testing.assert_array_equal(v, v2)
+    assert (res.U0, res.K0, res.W0, res.U1, res.K1, res.W1) == (U0, K0, W0, U1, K1, W1)
+    g = ref.geometry(s.box, s.slices, s.rc)
+    oU, oK, oW = ref.energy(g, s.pos, s.vel)
+    assert res.U0 == pytest.approx(oU, rel=1e-12) and res.K0 == pytest.approx(oK, rel=1e-13)
+
+
+@pytest.mark.timeout(300)
+def test_failed_run_fails_alone_and_admission_respects_budget():
+    runs = requests(6, seed=13)
+    fps = [md.md_footprint_bytes(s.box, s.slices, s.rc, s.n) for _, s in runs]
+    budget = max(fps) * 2 + 1
+    sv = md.Server(budget, 8, quantum_steps=10)
+    try:
+        tickets = []
+        # the run with the most slices gets one atom that jumps 2.5 slice widths in a step
+        bad_index = int(np.argmax([s.slices for _, s in runs]))
+        assert runs[bad_index][1].slices >= 5
+        for i, (r, s) in enumerate(runs):
+            vel = s.vel.copy()
+            if i == bad_index:
+                vel[0] = [2.5 * s.box[0] / s.slices / s.dt, 0.0, 0.0]
+            tickets.append(sv.submit(s.box, s.slices, s.pos, vel, r.steps, precision=md.MD_FP32_FORCE))
+        peak = 0
+        done = {}
+        t0 = time.time()
+        while len(done) < len(tickets):
+            assert time.time() - t0 < 120
+            st = sv.stats()
+            peak = max(peak, st["bytes_in_use"])
+            assert st["bytes_in_use"] <= budget
+            for t in tickets:
+                if t not in done:
+                    rc, res = sv.poll(t)
+                    if rc != md.MD_PENDING:
+                        done[t] = rc
+            time.sleep(0.001)
+        for i, t in enumerate(tickets):
+            assert done[t] == (md.MD_EUNSTABLE if i == bad_index else md.MD_OK)
+    finally:
+        sv.close()
