@@ -9,6 +9,7 @@ the persistent kernel.  Inputs are resident in HBM before the timed region start
 Prints ONE JSON line.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -27,19 +28,40 @@ METRIC = "atom-steps/s at 4M-atom LJ fluid, FP32-force vs FP64 plain; served p50
 FP32_PEAK = 157.3      # TFLOP/s, MI355X vector FP32 (packed) -- the figure the roofline uses
 FP64_PEAK = 78.6       # TFLOP/s, MI355X vector FP64
 HBM_PEAK = 8000.0      # GB/s
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_11289_amd", "csrc", "md_device.hip")
+
+# HBM traffic of one 100-step launch of the FP32-force persistent kernel on lj_fluid_4m,
+# from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) and the same
+# counters on a plain device copy of known size (profiles/persistent_kernel_lj_fluid_4m_fp32.md).
+# Valid only for the kernel source they were taken on (sha256 below); otherwise null.
+TRAFFIC = {
+    "source_sha256": "76b7b4a94cd4b6ca97789427c08a513b58c4788124252db690685957cc0680ce",
+    "workload": "lj_fluid_4m",
+    "steps_per_launch": 100,
+    "fetch_kib_per_launch": 68014325,      # FETCH_SIZE, mean of 3 dispatches
+    "write_kib_per_launch": 26110813,      # WRITE_SIZE, mean of 3 dispatches
+    "copy_fetch_factor": 0.50001,          # FETCH_SIZE KiB / KiB really read by a 1 GiB copy
+    "copy_write_factor": 1.00000,          # WRITE_SIZE KiB / KiB really written by it
+    "hbm_bytes_per_launch": 1.6603e+11,
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_leg(sysm, prec, steps, warmup, stream):
-    """Warm-up, then exactly `steps` steps in one md_step call bracketed by syncs."""
+def source_sha():
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+
+
+def timed_leg(sysm, prec, steps, warmup, stream, launch_steps):
+    """Warm-up, then exactly `steps` steps in one md_step call bracketed by syncs.
+    Every persistent launch (warm-up and timed) covers `launch_steps` steps."""
     import torch
 
     sim = md.Sim(sysm.box, sysm.slices, sysm.rc, sysm.dt, prec)
     sim.set_stream(stream.cuda_stream)
-    sim.set_option(md.OPT_MAX_STEPS_PER_LAUNCH, max(steps, warmup, 1))
+    sim.set_option(md.OPT_MAX_STEPS_PER_LAUNCH, launch_steps)
     sim.load(sysm.pos, sysm.vel)
     if warmup:
         sim.step(warmup)
@@ -150,17 +172,34 @@ def serve_leg(nreq, budget_bytes=96 << 30, max_runs=64):
     }
 
 
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="lj_fluid_4m", choices=sorted(inputs.WORKLOADS))
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--drift-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-drift", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--launch-steps", type=int, default=100,
+                    help="steps per persistent launch (warm-up and timed launches alike)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the slice-streaming path is built and measured "
@@ -173,6 +212,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     stream = torch.cuda.Stream()
     log(f"[bench] generating {args.workload}")
     sysm = inputs.WORKLOADS[args.workload]()
@@ -184,14 +226,26 @@ def main():
         if args.fp32_only and prec == md.MD_FP64:
             continue
         log(f"[bench] timed leg {name}: warmup {args.warmup}, steps {args.steps}")
-        legs[name] = timed_leg(sysm, prec, args.steps, args.warmup, stream)
+        legs[name] = timed_leg(sysm, prec, args.steps, args.warmup, stream, args.launch_steps)
         log(f"[bench]   {legs[name]}")
 
     main_leg = legs["fp32_force"]
     T = main_leg["event_s"]
     value = n * args.steps / T
     flop_per_atom_step = 8.0 * main_leg["C"] + 14.0 * main_leg["P"]
-    achieved = flop_per_atom_step * n * args.steps / main_leg["kernel_s"] / 1e12
+    launch_s = main_leg["kernel_s"] / max(main_leg["launches"], 1)
+    steps_per_launch = args.steps / max(main_leg["launches"], 1)
+    achieved = flop_per_atom_step * n * steps_per_launch / launch_s / 1e12
+    traffic = None          # measured HBM GB/s of the dominant kernel (rocprofv3 counters)
+    traffic_detail = None
+    if (TRAFFIC and TRAFFIC["source_sha256"] == source_sha() and sysm.name == TRAFFIC["workload"]
+            and int(steps_per_launch) == TRAFFIC["steps_per_launch"]):
+        hbm_bytes = TRAFFIC["hbm_bytes_per_launch"]
+        traffic = hbm_bytes / launch_s / 1e9
+        traffic_detail = {"unit": "GB/s", "hbm_bytes_per_launch": hbm_bytes,
+                          "frac_hbm_peak": traffic / HBM_PEAK,
+                          "bytes_per_atom_step": hbm_bytes / (n * steps_per_launch),
+                          "algorithmic_bytes_per_atom_step": 104.0}
     out = {
         "metric": METRIC,
         "value": value,
@@ -207,7 +261,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": sysm.name, "n_atoms": n, "box": list(sysm.box),
                    "slices": sysm.slices, "rc": sysm.rc, "dt": sysm.dt,
-                   "rho": 0.8, "T": 1.0, "precision": "fp32_force"},
+                   "rho": sysm.meta.get("rho"), "T": sysm.meta.get("T"), "precision": "fp32_force",
+                   "steps_per_launch": args.launch_steps},
         "pair_interactions_per_s": main_leg["P"] * n * args.steps / T,
         "candidates_per_atom": main_leg["C"],
         "in_range_per_atom": main_leg["P"],
@@ -217,9 +272,12 @@ def main():
             "peak": FP32_PEAK,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK,
-            "traffic": None,
-            "kernel": "persistent_kernel<1>",
-            "kernel_avg_ms": 1e3 * main_leg["kernel_s"] / max(main_leg["launches"], 1),
+            "traffic": traffic,
+            "traffic_detail": traffic_detail,
+            "kernel": "persistent_kernel<1, false>",
+            "kernel_avg_ms": 1e3 * launch_s,
+            "launches": main_leg["launches"],
+            "steps_per_launch": steps_per_launch,
             "flop_per_atom_step": flop_per_atom_step,
         },
     }

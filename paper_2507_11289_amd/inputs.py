@@ -170,7 +170,8 @@ def homogeneous(n: int, rho: float, T: float, seed: int, aspect=(1.0, 1.0, 1.0))
     pos = np.ascontiguousarray(remove_vacancies(sites, n, st))
     jitter(pos, box, st)
     vel = np.ascontiguousarray(maxwell_boltzmann(n, T, st))
-    return box, pos, vel, {"fcc": counts, "vacancies": 4 * counts[0] * counts[1] * counts[2] - n}
+    return box, pos, vel, {"fcc": counts, "vacancies": 4 * counts[0] * counts[1] * counts[2] - n,
+                           "rho": rho, "T": T}
 
 
 def slab(n: int, rho_l: float, rho_v: float, T: float, seed: int, elong: float = 16.0):
@@ -197,6 +198,7 @@ def slab(n: int, rho_l: float, rho_v: float, T: float, seed: int, elong: float =
     jitter(pos, box, st)
     vel = np.ascontiguousarray(maxwell_boltzmann(n, T, st))
     meta = {"n_liquid": n_l, "n_vapour": n_v, "fcc_liquid": c_l, "fcc_vapour": c_v,
+            "rho": [rho_l, rho_v], "T": T,
             "vacancies_liquid": 4 * c_l[0] * c_l[1] * c_l[2] - n_l,
             "vacancies_vapour": 4 * c_v[0] * c_v[1] * c_v[2] - n_v}
     return box, pos, vel, meta
