@@ -178,6 +178,12 @@ void md_free(md_sim *s);
 const char *md_strerror(int status);
 const char *md_last_error(void);
 
+/* The per-step claim table a persistent launch deals items from (claim orders other than
+ * MD_ORDER_DATAFLOW): 2 * slices entries (phase << 15) | slice, phase 0 = force and
+ * integration of step t, phase 1 = finalisation of step t+1.  MD_ORDER_SWEEP follows the
+ * stage order of Table 1: after slice k is integrated, slice k-1 is complete.  Host-only. */
+int md_claim_table(int slices, int order, uint64_t seed, uint16_t *out);
+
 /* Device bytes md_init + md_load would allocate for this system (for admission). */
 int64_t md_footprint_bytes(const double box[3], int slices, double rc, int64_t n);
 

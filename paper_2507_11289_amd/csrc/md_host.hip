@@ -198,6 +198,14 @@ static std::vector<uint16_t> make_order(int S, int kind, uint64_t seed) {
   return o;
 }
 
+extern "C" int md_claim_table(int slices, int order, uint64_t seed, uint16_t* out) {
+  if (slices < 3 || slices > 32767 || !out) return fail(MD_EINVAL, "bad arguments");
+  if (order < MD_ORDER_SWEEP || order > MD_ORDER_RANDOM) return fail(MD_EINVAL, "no table for this order");
+  std::vector<uint16_t> t = make_order(slices, order, seed);
+  std::memcpy(out, t.data(), t.size() * sizeof(uint16_t));
+  return MD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // device buffers of one simulation / run
 // ---------------------------------------------------------------------------

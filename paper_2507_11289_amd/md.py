@@ -86,6 +86,7 @@ _SIGS = {
     "md_strerror": ([C.c_int], C.c_char_p),
     "md_last_error": ([], C.c_char_p),
     "md_footprint_bytes": ([C.POINTER(C.c_double), C.c_int, C.c_double, C.c_int64], C.c_int64),
+    "md_claim_table": ([C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_uint16)], C.c_int),
     "md_server_create": ([C.c_size_t, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
     "md_server_create_ex": ([C.c_size_t, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
     "md_submit": ([C.c_void_p, C.POINTER(md_run_desc), C.POINTER(C.c_uint64)], C.c_int),
@@ -143,6 +144,14 @@ def md_strerror(code: int) -> str:
 def md_footprint_bytes(box, slices, rc, n) -> int:
     b = (C.c_double * 3)(*box)
     return lib().md_footprint_bytes(b, int(slices), float(rc), int(n))
+
+
+def md_claim_table(slices: int, order: int, seed: int = 1) -> np.ndarray:
+    """Per-step claim table as (phase, slice) pairs, shape (2*slices, 2)."""
+    t = np.zeros(2 * slices, np.uint16)
+    _check(lib().md_claim_table(int(slices), int(order), int(seed), t.ctypes.data_as(C.POINTER(C.c_uint16))),
+           "md_claim_table")
+    return np.stack([t >> 15, t & 0x7FFF], axis=1).astype(np.int64)
 
 
 class Sim:
