@@ -65,7 +65,7 @@ def test_sweep_order_follows_table_1(N):
         assert worker == stage - 2 and send == stage - 3
         assert pos[(1, send - 1)] == pos[(0, worker - 1)] + 1
         checked += 1
-    assert checked >= 3
+    assert checked == 2   # the printed interior rows: stage 5 and stage N
     # integration sweeps the slices in ascending order, as the worker does
     integ = [s for ph, s in t if ph == 0]
     assert integ == list(range(N))
