@@ -381,17 +381,47 @@ static double wrap1(double x, double L)
     return x;
 }
 
-int oracle_run(const orc_geom *g, int64_t n, double *pos, double *vel, double *F, double dt,
-               int64_t nsteps, int64_t every, double *elog, int64_t *nsamples,
-               int32_t *miglog, int64_t *steps_done)
+/* ------------------------------------------------------------------------
+ * Velocity-scaling thermostat (Sec. 4: a scale factor for the velocities is computed
+ * from the new velocities and applied before the positions are advanced; Sec. 5 runs
+ * the canonical ensemble with it).  The factor belongs to one slice -- the unit of
+ * work the kernels of Sec. 4 process -- and brings that slice's kinetic temperature to
+ * the target:  T_s = 2 K_s / (3 n_s),  lambda_s = sqrt(T0 / T_s)
+ *                                              = sqrt(3 n_s T0 / (2 K_s)),
+ * with K_s = sum over the slice's atoms of |v(t)|^2 / 2 (unit mass, k_B = 1).  A slice
+ * without atoms or without motion keeps its velocities (lambda = 1).  On the
+ * synchronous state the scaling is the first operation of a step, applied to v(t)
+ * of the atoms by the slice that holds them at time t.
+ * ------------------------------------------------------------------------ */
+static void thermostat_slices(const orc_geom *g, int64_t n, double *vel, const int32_t *slice, double T0,
+                              double *Ks, int64_t *ns, double *lam)
 {
-    if (!g || n < 0 || nsteps < 0 || !(dt > 0.0) || (n > 0 && (!pos || !vel || !F)))
+    for (int s = 0; s < g->S; s++) { Ks[s] = 0.0; ns[s] = 0; }
+    for (int64_t i = 0; i < n; i++) {
+        const double *v = vel + 3 * i;
+        Ks[slice[i]] += 0.5 * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+        ns[slice[i]]++;
+    }
+    for (int s = 0; s < g->S; s++)
+        lam[s] = (ns[s] > 0 && Ks[s] > 0.0) ? sqrt((3.0 * (double)ns[s] * T0) / (2.0 * Ks[s])) : 1.0;
+    for (int64_t i = 0; i < n; i++)
+        for (int d = 0; d < 3; d++) vel[3 * i + d] *= lam[slice[i]];
+}
+
+static int run_impl(const orc_geom *g, int64_t n, double *pos, double *vel, double *F, double dt,
+                    int64_t nsteps, double T0, int64_t every, double *elog, int64_t *nsamples,
+                    int32_t *miglog, int64_t *steps_done)
+{
+    if (!g || n < 0 || nsteps < 0 || !(dt > 0.0) || (n > 0 && (!pos || !vel || !F)) || !(T0 >= 0.0) ||
+        !isfinite(T0))
         return ORC_EINVAL;
     size_t nn = (size_t)(n > 0 ? n : 1);
     double *uh = malloc(sizeof(double) * nn), *wh = malloc(sizeof(double) * nn);
     int32_t *s_old = malloc(sizeof(int32_t) * nn), *s_new = malloc(sizeof(int32_t) * nn);
-    if (!uh || !wh || !s_old || !s_new) {
-        free(uh); free(wh); free(s_old); free(s_new);
+    double *Ks = malloc(sizeof(double) * (size_t)g->S), *lam = malloc(sizeof(double) * (size_t)g->S);
+    int64_t *ns_ = malloc(sizeof(int64_t) * (size_t)g->S);
+    if (!uh || !wh || !s_old || !s_new || !Ks || !lam || !ns_) {
+        free(uh); free(wh); free(s_old); free(s_new); free(Ks); free(lam); free(ns_);
         return ORC_ENOMEM;
     }
     const double hdt = 0.5 * dt;
@@ -405,6 +435,7 @@ int oracle_run(const orc_geom *g, int64_t n, double *pos, double *vel, double *F
     }
     for (int64_t step = 0; step < nsteps && !status; step++) {
         oracle_bin(g, n, pos, NULL, s_old, NULL);
+        if (T0 > 0.0) thermostat_slices(g, n, vel, s_old, T0, Ks, ns_, lam);
         int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
         for (int64_t i = 0; i < n; i++) {
@@ -454,6 +485,40 @@ int oracle_run(const orc_geom *g, int64_t n, double *pos, double *vel, double *F
     }
     if (nsamples) *nsamples = ns;
     if (steps_done) *steps_done = done;
-    free(uh); free(wh); free(s_old); free(s_new);
+    free(uh); free(wh); free(s_old); free(s_new); free(Ks); free(lam); free(ns_);
     return status;
+}
+
+int oracle_run(const orc_geom *g, int64_t n, double *pos, double *vel, double *F, double dt,
+               int64_t nsteps, int64_t every, double *elog, int64_t *nsamples,
+               int32_t *miglog, int64_t *steps_done)
+{
+    return run_impl(g, n, pos, vel, F, dt, nsteps, 0.0, every, elog, nsamples, miglog, steps_done);
+}
+
+int oracle_run_nvt(const orc_geom *g, int64_t n, double *pos, double *vel, double *F, double dt,
+                   int64_t nsteps, double T0, int64_t every, double *elog, int64_t *nsamples,
+                   int32_t *miglog, int64_t *steps_done)
+{
+    if (!(T0 > 0.0)) return ORC_EINVAL;
+    return run_impl(g, n, pos, vel, F, dt, nsteps, T0, every, elog, nsamples, miglog, steps_done);
+}
+
+int oracle_slice_scale(const orc_geom *g, int64_t n, const double *pos, double *vel, double T0,
+                       double *lam)
+{
+    if (!g || n < 0 || (n > 0 && (!pos || !vel)) || !(T0 > 0.0) || !isfinite(T0)) return ORC_EINVAL;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t *sl = malloc(sizeof(int32_t) * nn);
+    double *Ks = malloc(sizeof(double) * (size_t)g->S), *lm = malloc(sizeof(double) * (size_t)g->S);
+    int64_t *ns_ = malloc(sizeof(int64_t) * (size_t)g->S);
+    if (!sl || !Ks || !lm || !ns_) {
+        free(sl); free(Ks); free(lm); free(ns_);
+        return ORC_ENOMEM;
+    }
+    oracle_bin(g, n, pos, NULL, sl, NULL);
+    thermostat_slices(g, n, vel, sl, T0, Ks, ns_, lm);
+    if (lam) memcpy(lam, lm, sizeof(double) * (size_t)g->S);
+    free(sl); free(Ks); free(lm); free(ns_);
+    return 0;
 }

@@ -83,6 +83,20 @@ int oracle_run(const orc_geom *g, int64_t n, double *pos, double *vel, double *F
                int64_t nsteps, int64_t every, double *elog, int64_t *nsamples,
                int32_t *miglog, int64_t *steps_done);
 
+/* The same trajectory under the velocity-scaling thermostat of Sec. 4 / Sec. 5 at
+ * temperature T0 > 0: at the start of every step, the velocities v(t) of the atoms of
+ * each slice are scaled by lambda_s = sqrt(3 n_s T0 / (2 K_s)) (lambda_s = 1 for a
+ * slice without atoms or kinetic energy), slices taken from the positions at t.
+ * Energy samples report K of the unscaled v(t). */
+int oracle_run_nvt(const orc_geom *g, int64_t n, double *pos, double *vel, double *F, double dt,
+                   int64_t nsteps, double T0, int64_t every, double *elog, int64_t *nsamples,
+                   int32_t *miglog, int64_t *steps_done);
+
+/* One thermostat scaling of vel in place (slices from pos); lam[S] receives the factors
+ * (may be NULL). */
+int oracle_slice_scale(const orc_geom *g, int64_t n, const double *pos, double *vel, double T0,
+                       double *lam);
+
 void oracle_set_threads(int nthreads);
 int oracle_get_threads(void);
 

@@ -55,6 +55,9 @@ def lib():
         L.oracle_energy.argtypes = [gp, C.c_int64, dp, dp, dp, dp, dp]
         L.oracle_run.argtypes = [gp, C.c_int64, dp, dp, dp, C.c_double, C.c_int64, C.c_int64,
                                  dp, ip, i32p, ip]
+        L.oracle_run_nvt.argtypes = [gp, C.c_int64, dp, dp, dp, C.c_double, C.c_int64, C.c_double,
+                                     C.c_int64, dp, ip, i32p, ip]
+        L.oracle_slice_scale.argtypes = [gp, C.c_int64, dp, dp, C.c_double, dp]
         L.oracle_set_threads.argtypes = [C.c_int]
         L.oracle_set_threads.restype = None
         L.oracle_get_threads.restype = C.c_int
@@ -163,8 +166,9 @@ def energy(g: Geom, pos, vel):
     return U.value, K.value, W.value
 
 
-def run(g: Geom, pos, vel, dt, nsteps, every=0, miglog=False, check=True):
-    """Trajectory from {pos, vel}.  Returns dict(pos, vel, F, elog[t,U,K,W], miglog, status)."""
+def run(g: Geom, pos, vel, dt, nsteps, every=0, miglog=False, check=True, thermostat=None):
+    """Trajectory from {pos, vel}.  Returns dict(pos, vel, F, elog[t,U,K,W], miglog, status).
+    thermostat=T0 runs under the per-slice velocity-scaling thermostat."""
     pos = _f64(pos, (-1, 3)).copy()
     vel = _f64(vel, (-1, 3)).copy()
     n = len(pos)
@@ -173,14 +177,28 @@ def run(g: Geom, pos, vel, dt, nsteps, every=0, miglog=False, check=True):
     elog = np.zeros((max(cap, 1), 4))
     mig = np.zeros((max(nsteps, 1), g.S, 2), np.int32) if miglog else None
     ns, done = C.c_int64(), C.c_int64()
-    rc = lib().oracle_run(C.byref(g), n, _p(pos), _p(vel), _p(F), float(dt), int(nsteps),
-                          int(every), _p(elog), C.byref(ns), _p(mig, C.c_int32),
-                          C.byref(done))
+    if thermostat is None:
+        rc = lib().oracle_run(C.byref(g), n, _p(pos), _p(vel), _p(F), float(dt), int(nsteps),
+                              int(every), _p(elog), C.byref(ns), _p(mig, C.c_int32),
+                              C.byref(done))
+    else:
+        rc = lib().oracle_run_nvt(C.byref(g), n, _p(pos), _p(vel), _p(F), float(dt), int(nsteps),
+                                  float(thermostat), int(every), _p(elog), C.byref(ns),
+                                  _p(mig, C.c_int32), C.byref(done))
     if check:
         _check(rc)
     return {"pos": pos, "vel": vel, "F": F, "elog": elog[: ns.value],
             "miglog": None if mig is None else mig[:nsteps], "status": rc,
             "steps_done": done.value}
+
+
+def slice_scale(g: Geom, pos, vel, T0):
+    """One per-slice thermostat scaling.  Returns (scaled velocities, lambda[S])."""
+    pos = _f64(pos, (-1, 3))
+    vel = _f64(vel, (-1, 3)).copy()
+    lam = np.zeros(g.S)
+    _check(lib().oracle_slice_scale(C.byref(g), len(pos), _p(pos), _p(vel), float(T0), _p(lam)))
+    return vel, lam
 
 
 def force_error(F_test, F_ref, scale):
