@@ -274,7 +274,7 @@ def main():
             "frac": achieved / FP32_PEAK,
             "traffic": traffic,
             "traffic_detail": traffic_detail,
-            "kernel": "persistent_kernel<1, false>",
+            "kernel": "persistent_f32_lean",
             "kernel_avg_ms": 1e3 * launch_s,
             "launches": main_leg["launches"],
             "steps_per_launch": steps_per_launch,

@@ -156,7 +156,8 @@ int md_get_migration_log(md_sim *s, int64_t cap_steps, int32_t *log, int64_t *st
 
 /* One work item of a persistent launch (MD_OPT_TRACE): which item, on which compute
  * unit, and when (device wall clock ticks) it was claimed, found its inputs ready,
- * and finished.  phase 0 = force/integrate of step k, 1 = finalise of step k+1. */
+ * and finished.  phase 0 = force/integrate of step k (force only with the thermostat),
+ * 1 = finalise of step k+1, 2 = thermostat integrate of step k. */
 typedef struct md_trace_rec {
     uint32_t k, slice, chunk, phase;
     uint32_t hw_id;            /* hardware id register of the wave that ran it */
@@ -169,6 +170,21 @@ int md_get_trace(md_sim *s, int64_t cap, md_trace_rec *out, int64_t *count, doub
 
 int md_get_stats(md_sim *s, md_stats *out);
 int md_set_option(md_sim *s, int key, int64_t value);
+
+/* Velocity-scaling thermostat (Sec. 4: kernels md_thermo_a/md_thermo_b compute a scale
+ * factor from the new velocities and md_v3b applies it before the positions advance;
+ * Sec. 5 simulates the canonical ensemble with it).  With temperature T0 > 0 every
+ * later step starts by scaling the velocities v(t) of the atoms of each slice i by
+ *     lambda_i = sqrt(3 n_i T0 / (2 K_i)),   K_i = sum over the slice of |v(t)|^2 / 2,
+ * (lambda_i = 1 when the slice holds no atoms or no kinetic energy), so that the
+ * slice's kinetic temperature 2 K / (3 n) becomes T0; the factor of a slice depends
+ * only on that slice.  T0 = 0 switches it off (NVE).  Energy samples and md_get_state
+ * report the unscaled v(t).  Each step then runs as a force pass over the slice, then
+ * an integrate pass once the whole slice's K is known (24 B of forces per atom kept in
+ * between; device memory is allocated at the next md_step).  Requires the default
+ * MD_ORDER_DATAFLOW scheduler: md_step returns MD_EINVAL under another claim order.
+ * Errors: MD_EINVAL for a NULL handle or a negative or non-finite temperature. */
+int md_set_thermostat(md_sim *s, double temperature);
 
 /* Use a caller-owned hipStream_t (passed as void*) for every later launch and copy;
  * NULL returns to the library's own stream. */

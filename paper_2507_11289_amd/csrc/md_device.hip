@@ -119,6 +119,7 @@ constexpr int BZ = WAVES;               // cells per block, one per wave
 constexpr int BLAYERS = BZ + 2;         // staged z layers
 constexpr int BCELLS = 9 * BLAYERS;     // staged cells
 constexpr int CAPB = 27 * CELL_CAP;     // staged atoms at most (one full neighbourhood)
+constexpr int QPAD = 16;                // far sentinels after the staged atoms (FP32)
 
 struct BlockHdr {
   int nb_cell[BCELLS];     // global cell of staged cell m
@@ -133,7 +134,7 @@ template <int PREC> struct BlockLDS;
 template <> struct BlockLDS<1> {  // FP32: positions relative to the block origin + tag
   BlockHdr h;
   union {
-    float4 q[CAPB];
+    float4 q[CAPB + QPAD];
     double red[WAVES][64 * 6];
   };
 };
@@ -175,18 +176,24 @@ template <class R> __device__ __forceinline__ R force_factor(R ir2, R ir6) {
   return (ir6 * (ir6 * (R)48 - (R)24)) * ir2;
 }
 
-// FP32 pair for one i-atom against one staged candidate (Algorithm 1 loop body).
-// In range for certain when 0 < r2 <= rc2_lo (r2 == 0 only for the atom itself);
-// pairs with rc2_lo < r2 <= rc2_hi go into the wave mask `band` and are decided again
-// in FP64 afterwards.
+// Pre-filter of one pair: shifts bit (r2 < rc2_pre) into the mask.  The threshold is
+// folded into the FMA chain; the sign of r2 - rc2_pre is the bit (a superset test:
+// the exact decision follows in pair32_in).
+__device__ __forceinline__ unsigned prefilter32(const float4& qi, const float4& q, float pre, unsigned m) {
+  const float dx = qi.x - q.x, dy = qi.y - q.y, dz = qi.z - q.z;
+  const float d = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, -pre)));
+  return __builtin_amdgcn_alignbit(m, __float_as_uint(d), 31);
+}
+
+// FP32 pair term of a pre-filtered pair (Algorithm 1 loop body), the range decision
+// and arithmetic of pair32.  Returns true for a guard-band pair (decided again in FP64).
 template <bool ENERGY, bool COUNT>
-__device__ __forceinline__ void pair32(float qx, float qy, float qz, const float4& q, unsigned lo_bits,
-                                       unsigned hi_bits, float ucf, Acc<float>& a, unsigned long long& band) {
-  const float dx = qx - q.x, dy = qy - q.y, dz = qz - q.z;
+__device__ __forceinline__ bool pair32_in(const float4& qi, const float4& q, unsigned lo_bits, unsigned hi_bits,
+                                          float ucf, Acc<float>& a) {
+  const float dx = qi.x - q.x, dy = qi.y - q.y, dz = qi.z - q.z;
   const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
   const unsigned rb = __float_as_uint(r2) - 1u;
   const bool in = rb < lo_bits;
-  band |= __ballot(rb < hi_bits) & ~__ballot(in);
   const float ir2 = __builtin_amdgcn_rcpf(r2);
   const float ir6 = ir2 * ir2 * ir2;
   float fr = force_factor(ir2, ir6);
@@ -199,6 +206,7 @@ __device__ __forceinline__ void pair32(float qx, float qy, float qz, const float
     a.w += in ? (double)(24.0f * ir6 * fmaf(2.0f, ir6, -1.0f)) : 0.0;
   }
   if (COUNT) a.pc += in ? 1u : 0u;
+  return !in & (rb < hi_bits);
 }
 
 // The same FP32 pair term, added unconditionally (guard-band pairs found in range).
@@ -295,6 +303,11 @@ __device__ int stage_block(const DGeom& g, const unsigned char* cells, const uin
   // FP32 origin: the column corner at the start of z0's aligned group of BZ cells, so a
   // pair's FP32 arithmetic depends on the cell only, not on how cells form blocks
   const double ox = gx * g.l[0], oy = gy * g.l[1], oz = (z0 - z0 % BZ) * g.l[2];
+  if constexpr (PREC == 1) {
+    // far sentinels after the last staged atom: a pair-loop read past the end of the
+    // list finds no partner in range
+    if (tid < QPAD) L.q[L.h.pre[9 * (nb + 2)] + tid] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+  }
   for (int mb = 0; mb < 9 * (nb + 2); mb += WG / 4) {
     const int m = mb + ms;
     if (m >= 9 * (nb + 2)) break;
@@ -369,25 +382,46 @@ __device__ void block_force(const DGeom& g, const unsigned char* cells, int gx, 
     const int si = L.h.pre[ci];  // own atoms in the staged list
     const unsigned lo_bits = __float_as_uint(g.rc2_lo_f), hi_bits = __float_as_uint(g.rc2_hi_f);
     if constexpr (PREC == 1) {
-      const float4 qa = L.q[si + ia];
-      // a missing second atom sits far away and never interacts
-      const float4 qb = has_b ? L.q[si + ib_] : make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+      // a missing atom (second atom of the lane, or a lane without a group) sits far
+      // away and never interacts
+      const float4 far = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+      const float4 qa = grp < G ? L.q[si + ia] : far;
+      const float4 qb = grp < G && has_b ? L.q[si + ib_] : far;
       unsigned long long band_a = 0ull, band_b = 0ull;
-      int f = f0;
-      // two candidates per iteration (four pairs), then the remainder
-      for (; f + G < fe; f += 2 * G) {
-        const float4 q0 = L.q[f];
-        const float4 q1 = L.q[f + G];
-        pair32<ENERGY, COUNT>(qa.x, qa.y, qa.z, q0, lo_bits, hi_bits, g.uc_f, A, band_a);
-        pair32<ENERGY, COUNT>(qb.x, qb.y, qb.z, q0, lo_bits, hi_bits, g.uc_f, B, band_b);
-        pair32<ENERGY, COUNT>(qa.x, qa.y, qa.z, q1, lo_bits, hi_bits, g.uc_f, A, band_a);
-        pair32<ENERGY, COUNT>(qb.x, qb.y, qb.z, q1, lo_bits, hi_bits, g.uc_f, B, band_b);
+      bool flag_a = false, flag_b = false;
+      // Two passes over batches of up to 32 candidate slots of this lane (slots f0 + c G).
+      // Pass 1 keeps a bit per pair, set when r2 < rc2_pre (a superset of the pairs in
+      // range); pass 2 evaluates exactly those pairs, in slot order, with the same FP32
+      // arithmetic and range decision a pair-by-pair loop would use.  Every lane runs
+      // the same pass-1 trip count: a read past the end of the window lands in the next
+      // z layer (two layers above the own cell, out of range) or in the far sentinels.
+      const int nmax = __builtin_amdgcn_readfirstlane((total + G - 1) / G);
+      const int stride = __builtin_amdgcn_readfirstlane(G);
+      for (int cb = 0; cb < nmax; cb += 32) {
+        const int cn = min(32, nmax - cb);
+        const int fb = (grp < G ? f0 : beg) + cb * stride;
+        unsigned ma = 0u, mb = 0u;
+#pragma unroll 4
+        for (int c = 0; c < cn; c++) {
+          const float4 q = L.q[fb + c * stride];
+          ma = prefilter32(qa, q, g.rc2_pre_f, ma);
+          mb = prefilter32(qb, q, g.rc2_pre_f, mb);
+        }
+        ma <<= 32 - cn;
+        mb <<= 32 - cn;
+        while (ma) {
+          const int m = __clz(ma);
+          ma ^= 0x80000000u >> m;
+          flag_a |= pair32_in<ENERGY, COUNT>(qa, L.q[fb + __mul24(m, stride)], lo_bits, hi_bits, g.uc_f, A);
+        }
+        while (mb) {
+          const int m = __clz(mb);
+          mb ^= 0x80000000u >> m;
+          flag_b |= pair32_in<ENERGY, COUNT>(qb, L.q[fb + __mul24(m, stride)], lo_bits, hi_bits, g.uc_f, B);
+        }
       }
-      if (f < fe) {
-        const float4 q0 = L.q[f];
-        pair32<ENERGY, COUNT>(qa.x, qa.y, qa.z, q0, lo_bits, hi_bits, g.uc_f, A, band_a);
-        pair32<ENERGY, COUNT>(qb.x, qb.y, qb.z, q0, lo_bits, hi_bits, g.uc_f, B, band_b);
-      }
+      band_a = __ballot(flag_a);
+      band_b = __ballot(flag_b);
       // guard band: decide those pairs in FP64 exactly as the FP64 path would
       if (band_a | band_b) {
         const double* iblk = cblk(cells, o.c);
@@ -440,45 +474,53 @@ __device__ void block_force(const DGeom& g, const unsigned char* cells, int gx, 
   // every wave is done with the staged positions; the same LDS now holds the partials
   __syncthreads();
   if (n_i > 0) {
-    double sa[6] = {0, 0, 0, 0, 0, 0}, sb[6] = {0, 0, 0, 0, 0, 0};
+    // values per lane: force (3) and, when sampled or counted, energy, virial, count
+    constexpr int NV = (ENERGY || COUNT) ? 6 : 3;
+    double sa[NV], sb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) sa[v] = sb[v] = 0.0;
     double* red = L.red[w];
     for (int h = 0; h < 2; h++) {
       const Acc<R>& X = h == 0 ? A : B;
       wave_sync();
-      red[lane * 6 + 0] = (double)X.fx;
-      red[lane * 6 + 1] = (double)X.fy;
-      red[lane * 6 + 2] = (double)X.fz;
-      red[lane * 6 + 3] = X.u;
-      red[lane * 6 + 4] = X.w;
-      red[lane * 6 + 5] = (double)X.pc;
+      red[lane * NV + 0] = (double)X.fx;
+      red[lane * NV + 1] = (double)X.fy;
+      red[lane * NV + 2] = (double)X.fz;
+      if constexpr (NV == 6) {
+        red[lane * NV + 3] = X.u;
+        red[lane * NV + 4] = X.w;
+        red[lane * NV + 5] = (double)X.pc;
+      }
       wave_sync();
       if (lane < P) {
         double* s = h == 0 ? sa : sb;
         for (int q = 0; q < G; q++) {
-          const double* r = red + (lane + q * P) * 6;
+          const double* r = red + (lane + q * P) * NV;
 #pragma unroll
-          for (int v = 0; v < 6; v++) s[v] += r[v];
+          for (int v = 0; v < NV; v++) s[v] += r[v];
         }
       }
     }
     wave_sync();
     if (lane < P) {
 #pragma unroll
-      for (int v = 0; v < 6; v++) red[lane * 6 + v] = sa[v];
+      for (int v = 0; v < NV; v++) red[lane * NV + v] = sa[v];
       if (lane + P < n_i) {
 #pragma unroll
-        for (int v = 0; v < 6; v++) red[(lane + P) * 6 + v] = sb[v];
+        for (int v = 0; v < NV; v++) red[(lane + P) * NV + v] = sb[v];
       }
     }
     wave_sync();
     if (lane < n_i) {
-      const double* r = red + lane * 6;
+      const double* r = red + lane * NV;
       o.fx = r[0];
       o.fy = r[1];
       o.fz = r[2];
-      o.uh = 0.5 * r[3];
-      o.wh = 0.5 * r[4];
-      o.pc = (unsigned)r[5];
+      if constexpr (NV == 6) {
+        o.uh = 0.5 * r[3];
+        o.wh = 0.5 * r[4];
+        o.pc = (unsigned)r[5];
+      }
     }
   }
 }
@@ -507,12 +549,15 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
 // Per-item accumulators of one wave.
 struct ItemAcc {
   double u, w, k;                 // per lane (energy steps)
+  double kt;                      // per lane: kinetic energy of v(t) (thermostat)
+  unsigned nt;                    // per lane: atoms (thermostat)
   unsigned long long cand, inr;   // per lane (count mode)
   unsigned left, right;           // uniform migration counts
 };
 
 __device__ __forceinline__ void acc_zero(ItemAcc& a) {
-  a.u = a.w = a.k = 0.0;
+  a.u = a.w = a.k = a.kt = 0.0;
+  a.nt = 0;
   a.cand = a.inr = 0;
   a.left = a.right = 0;
 }
@@ -526,9 +571,11 @@ __device__ __forceinline__ void acc_zero(ItemAcc& a) {
 // stored: the same cell (kept in order), or appended to another cell -- possibly in
 // the left or right neighbour slice.
 // ---------------------------------------------------------------------------
-template <bool ENERGY, bool COUNT>
+// SCALE: the thermostat factor lam multiplies v(t) first (the forces come from the
+// thermostat's force pass; energies were sampled there).
+template <bool ENERGY, bool COUNT, bool SCALE>
 __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first, ItemAcc& acc,
-                        uint32_t* abort_flag) {
+                        uint32_t* abort_flag, double lam) {
   const DGeom& g = ra.g;
   const int lane = __lane_id();
   const int dst = src ^ 1;
@@ -553,6 +600,7 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first
     for (int d = 0; d < 3; d++) {
       const double v = ib[(3 + d) * CELL_CAP + lane];
       vf[d] = first ? v : __dadd_rn(v, __dmul_rn(g.hdt, F[d]));
+      if (SCALE) vf[d] = __dmul_rn(lam, vf[d]);
     }
     if (ENERGY) {
       acc.k += 0.5 * __dadd_rn(__dadd_rn(__dmul_rn(vf[0], vf[0]), __dmul_rn(vf[1], vf[1])),
@@ -608,6 +656,43 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first
   if (lane == 0) ra.ncnt[dst][c] = (uint32_t)__popcll(sm);
   acc.left += (unsigned)__popcll(__ballot(ok && dir == 1));
   acc.right += (unsigned)__popcll(__ballot(ok && dir == 2));
+}
+
+// Force pass of a thermostat step (kernels md_v3a, md_v3aa, md_thermo_a): v(t) of
+// every atom of the cell enters the slice's kinetic energy; F(t) is kept for the
+// integrate pass, which runs once the whole slice is known (its scale factor needs
+// every atom of the slice).
+template <bool ENERGY, bool COUNT>
+__device__ void p2_force_tail(const RunArgs& ra, const ForceOut& o, int src, int first, ItemAcc& acc) {
+  const DGeom& g = ra.g;
+  const int lane = __lane_id();
+  const int c = o.c;
+  if (c < 0 || lane >= o.n) return;
+  const double* ib = cblk(ra.cells[src], c);
+  const double F[3] = {o.fx, o.fy, o.fz};
+  double vf[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const double v = ib[(3 + d) * CELL_CAP + lane];
+    vf[d] = first ? v : __dadd_rn(v, __dmul_rn(g.hdt, F[d]));
+  }
+  const double ke =
+      0.5 * __dadd_rn(__dadd_rn(__dmul_rn(vf[0], vf[0]), __dmul_rn(vf[1], vf[1])), __dmul_rn(vf[2], vf[2]));
+  acc.kt += ke;
+  acc.nt += 1u;
+  if (ENERGY) {
+    acc.k += ke;
+    acc.u += o.uh;
+    acc.w += o.wh;
+  }
+  if (COUNT) {
+    acc.cand += (unsigned long long)(o.total - 1);
+    acc.inr += o.pc;
+  }
+  double* fb = ra.fbuf + (size_t)c * 3 * CELL_CAP;
+  fb[lane] = F[0];
+  fb[CELL_CAP + lane] = F[1];
+  fb[2 * CELL_CAP + lane] = F[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -692,15 +777,16 @@ struct Item {
   int run, k, phase, slice, chunk, go;
 };
 
+// phase: 0 force (+ integrate without the thermostat), 1 finalise, 2 thermostat integrate
 __device__ __forceinline__ unsigned long long enc_item(int run, int k, int phase, int slice, int chunk) {
-  return (1ull << 63) | ((unsigned long long)run << 48) | ((unsigned long long)k << 28) |
+  return (1ull << 63) | ((unsigned long long)run << 48) | ((unsigned long long)k << 29) |
          ((unsigned long long)phase << 27) | ((unsigned long long)slice << 12) | (unsigned long long)chunk;
 }
 
 __device__ __forceinline__ void dec_item(unsigned long long v, Item& it) {
   it.run = (int)((v >> 48) & 0x7fffull);
-  it.k = (int)((v >> 28) & 0xfffffull);
-  it.phase = (int)((v >> 27) & 1ull);
+  it.k = (int)((v >> 29) & 0x7ffffull);
+  it.phase = (int)((v >> 27) & 3ull);
   it.slice = (int)((v >> 12) & 0x7fffull);
   it.chunk = (int)(v & 0xfffull);
 }
@@ -722,9 +808,12 @@ __device__ bool wait_counters(const LaunchArgs& la, const uint32_t* cnt, int S, 
   return true;
 }
 
-template <int PREC, bool ENERGY, bool COUNT>
-__device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L, double (*s_red)[3],
-                            unsigned long long (*s_cnt)[4], uint32_t* abort_flag) {
+// Force item of slice i at step k (Algorithm 1 over the item's cells).  NVT: forces
+// and the kinetic energy of v(t) only; the integrate item follows.  Otherwise the
+// velocity-Verlet update and migration follow at once, cell by cell.
+template <int PREC, bool ENERGY, bool COUNT, bool NVT>
+__device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L, double (*s_red)[4],
+                            unsigned long long (*s_cnt)[5], uint32_t* abort_flag) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int src = (ra.par0 + it.k) & 1;
   const int first = (it.k == 0) ? ra.first : 0;
@@ -733,12 +822,13 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L
   ItemAcc acc;
   acc_zero(acc);
   for_blocks<PREC, ENERGY, COUNT>(ra.g, ra.cells[src], ra.ncnt[src], it.slice, b, e, L, [&](const ForceOut& o) {
-    p2_tail<ENERGY, COUNT>(ra, o, src, first, acc, abort_flag);
+    if (NVT) p2_force_tail<ENERGY, COUNT>(ra, o, src, first, acc);
+    else p2_tail<ENERGY, COUNT, false>(ra, o, src, first, acc, abort_flag, 1.0);
   });
   // wave reductions (fixed butterfly), then waves in order
-  double u = acc.u, w = acc.w, k = acc.k;
-  unsigned long long cc = acc.cand, pc = acc.inr;
-  if (ENERGY || COUNT) {
+  double u = acc.u, w = acc.w, k = acc.k, kt = acc.kt;
+  unsigned long long cc = acc.cand, pc = acc.inr, nt = acc.nt;
+  if (ENERGY || COUNT || NVT) {
     for (int off = 32; off >= 1; off >>= 1) {
       if (ENERGY) {
         u += __shfl_xor(u, off);
@@ -749,16 +839,22 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L
         cc += __shfl_xor(cc, off);
         pc += __shfl_xor(pc, off);
       }
+      if (NVT) {
+        kt += __shfl_xor(kt, off);
+        nt += __shfl_xor(nt, off);
+      }
     }
   }
   if (lane == 0) {
     s_red[wave][0] = u;
     s_red[wave][1] = k;
     s_red[wave][2] = w;
+    s_red[wave][3] = kt;
     s_cnt[wave][0] = acc.left;
     s_cnt[wave][1] = acc.right;
     s_cnt[wave][2] = cc;
     s_cnt[wave][3] = pc;
+    s_cnt[wave][4] = nt;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -775,6 +871,17 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L
       ep[0] = su;
       ep[1] = sk;
       ep[2] = sw;
+    }
+    if (NVT) {
+      double skt = 0;
+      unsigned long long snt = 0;
+      for (int q = 0; q < WAVES; q++) {
+        skt += s_red[q][3];
+        snt += s_cnt[q][4];
+      }
+      double* kp = ra.kpart + ((size_t)it.slice * ra.nch + it.chunk) * 2;
+      kp[0] = skt;
+      kp[1] = (double)snt;
     }
     unsigned long long left = 0, right = 0, c2 = 0, p2 = 0;
     for (int q = 0; q < WAVES; q++) {
@@ -798,22 +905,96 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L
   }
 }
 
-template <int PREC, bool FULL>
-__device__ void run_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& ws, double (*s_red)[3],
-                         unsigned long long (*s_cnt)[4]) {
+// Integrate item of a thermostat step (kernels md_thermo_b, md_v3b): the slice's scale
+// factor from the kinetic energy of all its force items (summed in chunk order), then
+// the velocity-Verlet update with v(t) scaled, and migration, cell by cell.
+__device__ void run_p2b_item(const RunArgs& ra, const Item& it, double* s_lam, unsigned long long (*s_cnt)[5],
+                             uint32_t* abort_flag) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int src = (ra.par0 + it.k) & 1;
+  const int first = (it.k == 0) ? ra.first : 0;
+  if (threadIdx.x == 0) {
+    double K = 0.0, n = 0.0;
+    const double* kp = ra.kpart + (size_t)it.slice * ra.nch * 2;
+    for (int ch = 0; ch < ra.nch; ch++) {
+      K += kp[2 * ch];
+      n += kp[2 * ch + 1];
+    }
+    *s_lam = (n > 0.0 && K > 0.0) ? __dsqrt_rn(__ddiv_rn(__dmul_rn(__dmul_rn(3.0, n), ra.thermo_T), __dmul_rn(2.0, K)))
+                                  : 1.0;
+  }
+  __syncthreads();
+  const double lam = *s_lam;
+  const int b = (int)((long long)ra.g.cps * it.chunk / ra.nch);
+  const int e = (int)((long long)ra.g.cps * (it.chunk + 1) / ra.nch);
+  const int cbase = it.slice * ra.g.cps;
+  ItemAcc acc;
+  acc_zero(acc);
+  for (int c = cbase + b + wave; c < cbase + e; c += WAVES) {
+    ForceOut o;
+    o.c = c;
+    o.n = (int)ra.ncnt[src][c];
+    o.total = 0;
+    o.pc = 0;
+    o.uh = o.wh = 0.0;
+    o.fx = o.fy = o.fz = 0.0;
+    if (lane < o.n) {
+      const double* fb = ra.fbuf + (size_t)c * 3 * CELL_CAP;
+      o.fx = fb[lane];
+      o.fy = fb[CELL_CAP + lane];
+      o.fz = fb[2 * CELL_CAP + lane];
+    }
+    p2_tail<false, false, true>(ra, o, src, first, acc, abort_flag, lam);
+  }
+  if (lane == 0) {
+    s_cnt[wave][0] = acc.left;
+    s_cnt[wave][1] = acc.right;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long left = 0, right = 0;
+    for (int q = 0; q < WAVES; q++) {
+      left += s_cnt[q][0];
+      right += s_cnt[q][1];
+    }
+    if (left) atomicAdd(ra.migcum + 2 * it.slice + 0, left);
+    if (right) atomicAdd(ra.migcum + 2 * it.slice + 1, right);
+    if (ra.miglog) {
+      if (left) atomicAdd(ra.miglog + ((size_t)it.k * ra.g.S + it.slice) * 2 + 0, (uint32_t)left);
+      if (right) atomicAdd(ra.miglog + ((size_t)it.k * ra.g.S + it.slice) * 2 + 1, (uint32_t)right);
+    }
+  }
+}
+
+// NVT: the kernel variant that also runs thermostat steps (ra.thermo_T > 0).
+template <int PREC, bool FULL, bool NVT>
+__device__ void run_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& ws, double (*s_red)[4],
+                         unsigned long long (*s_cnt)[5]) {
   const int wave = threadIdx.x >> 6;
+  const bool nvt = NVT && ra.thermo_T > 0.0;
   if (it.phase == 0) {
     const long long t = ra.t0 + it.k;
     const bool energy = ra.every > 0 && (t % ra.every) == 0;
     if (!FULL) {
-      run_p2_item<PREC, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+      if (NVT && nvt) run_p2_item<PREC, false, false, NVT>(ra, it, ws, s_red, s_cnt, ra.abort);
+      else run_p2_item<PREC, false, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+    } else if (NVT && nvt) {
+      if (ra.count) {
+        if (energy) run_p2_item<PREC, true, true, NVT>(ra, it, ws, s_red, s_cnt, ra.abort);
+        else run_p2_item<PREC, false, true, NVT>(ra, it, ws, s_red, s_cnt, ra.abort);
+      } else {
+        if (energy) run_p2_item<PREC, true, false, NVT>(ra, it, ws, s_red, s_cnt, ra.abort);
+        else run_p2_item<PREC, false, false, NVT>(ra, it, ws, s_red, s_cnt, ra.abort);
+      }
     } else if (ra.count) {
-      if (energy) run_p2_item<PREC, true, true>(ra, it, ws, s_red, s_cnt, ra.abort);
-      else run_p2_item<PREC, false, true>(ra, it, ws, s_red, s_cnt, ra.abort);
+      if (energy) run_p2_item<PREC, true, true, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+      else run_p2_item<PREC, false, true, false>(ra, it, ws, s_red, s_cnt, ra.abort);
     } else {
-      if (energy) run_p2_item<PREC, true, false>(ra, it, ws, s_red, s_cnt, ra.abort);
-      else run_p2_item<PREC, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+      if (energy) run_p2_item<PREC, true, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+      else run_p2_item<PREC, false, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
     }
+  } else if (NVT && it.phase == 2) {
+    run_p2b_item(ra, it, &s_red[0][0], s_cnt, ra.abort);
   } else {
     const int dst = (ra.par0 + it.k + 1) & 1;
     const int b = (int)((long long)ra.g.cps * it.chunk / ra.nch);
@@ -827,14 +1008,30 @@ __device__ void run_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& ws, 
 // a dependency set appends the dependent items (all chunks) to the queue.
 __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const Item& it) {
   const int S = ra.g.S;
+  const bool nvt = ra.thermo_T > 0.0;
+  if (nvt && it.phase == 0) {
+    // thermostat: the slice's integrate items wait for all of its force items
+    const unsigned needk = (unsigned)ra.nch * (unsigned)(it.k + 1);
+    const unsigned old = __hip_atomic_fetch_add(ra.cntK + it.slice, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1u != needk) return;
+    const unsigned long long base =
+        __hip_atomic_fetch_add(la.q_tail, (unsigned long long)ra.nch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int ch = 0; ch < ra.nch; ch++)
+      __hip_atomic_store(la.q + base + ch, enc_item(it.run, it.k, 2, it.slice, ch), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  // the step's update of slice i (phase 0, or 2 with the thermostat) counts towards the
+  // finalise of i-1, i, i+1; a finalise counts towards the next force items
+  const bool update = it.phase != 1;
   const unsigned need = 3u * (unsigned)ra.nch * (unsigned)(it.k + 1);
-  uint32_t* cnt = it.phase == 0 ? ra.cntF : ra.cntA;
+  uint32_t* cnt = update ? ra.cntF : ra.cntA;
   for (int d = -1; d <= 1; d++) {
     const int j = (it.slice + d + S) % S;
     const unsigned old = __hip_atomic_fetch_add(cnt + j, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (old + 1u != need) continue;
     int phase, k;
-    if (it.phase == 0) {
+    if (update) {
       phase = 1;  // finalise of step k+1
       k = it.k;
     } else {
@@ -851,11 +1048,12 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
 }
 
 // FULL = false: launches without energy samples or pair counting (fewer registers).
-template <int PREC, bool FULL>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void persistent_kernel(LaunchArgs la) {
+// NVT = true: launches with a thermostat run.
+template <int PREC, bool FULL, bool NVT>
+__device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
   __shared__ BlockLDS<PREC> ws;
-  __shared__ double s_red[WAVES][3];
-  __shared__ unsigned long long s_cnt[WAVES][4];
+  __shared__ double s_red[WAVES][4];
+  __shared__ unsigned long long s_cnt[WAVES][5];
   __shared__ Item s_it;
   __shared__ int s_ok;
   __shared__ long long s_ticket;
@@ -938,7 +1136,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void pe
     const int ok = s_ok;
     if (ok) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      run_item<PREC, FULL>(ra, it, ws, s_red, s_cnt);
+      run_item<PREC, FULL, NVT>(ra, it, ws, s_red, s_cnt);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
@@ -954,6 +1152,27 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void pe
     }
     __syncthreads();
   }
+}
+
+// The lean FP32 kernel is held to 128 VGPRs (4 waves per SIMD); the others take what
+// they need.
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void persistent_f32_lean(LaunchArgs la) {
+  persistent_body<1, false, false>(la);
+}
+__global__ __launch_bounds__(WG) void persistent_f32_full(LaunchArgs la) { persistent_body<1, true, false>(la); }
+__global__ __launch_bounds__(WG) void persistent_f64_lean(LaunchArgs la) { persistent_body<0, false, false>(la); }
+__global__ __launch_bounds__(WG) void persistent_f64_full(LaunchArgs la) { persistent_body<0, true, false>(la); }
+__global__ __launch_bounds__(WG) void persistent_f32_lean_nvt(LaunchArgs la) { persistent_body<1, false, true>(la); }
+__global__ __launch_bounds__(WG) void persistent_f32_full_nvt(LaunchArgs la) { persistent_body<1, true, true>(la); }
+__global__ __launch_bounds__(WG) void persistent_f64_lean_nvt(LaunchArgs la) { persistent_body<0, false, true>(la); }
+__global__ __launch_bounds__(WG) void persistent_f64_full_nvt(LaunchArgs la) { persistent_body<0, true, true>(la); }
+
+typedef void (*PersistentFn)(LaunchArgs);
+static PersistentFn persistent_fn(int prec, int full, int nvt) {
+  static const PersistentFn fns[2][2][2] = {
+      {{persistent_f64_lean, persistent_f64_lean_nvt}, {persistent_f64_full, persistent_f64_full_nvt}},
+      {{persistent_f32_lean, persistent_f32_lean_nvt}, {persistent_f32_full, persistent_f32_full_nvt}}};
+  return fns[prec == 1][full != 0][nvt != 0];
 }
 
 // Launch set-up: counters, abort flags, claim counter; in dataflow mode the queue holds
@@ -972,6 +1191,7 @@ __global__ void init_launch_kernel(LaunchArgs la) {
     for (long long s = i; s < ra.g.S; s += stride) {
       ra.cntA[s] = la.mode == 0 ? 0u : (uint32_t)ra.nch;
       ra.cntF[s] = 0u;
+      if (ra.cntK) ra.cntK[s] = 0u;
     }
     if (la.mode == 0 && ra.nsteps > 0) {
       const long long n0 = (long long)ra.g.S * ra.nch;
@@ -1150,33 +1370,22 @@ int launch_init(const LaunchArgs& la, long long work, void* stream) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int persistent_grid(int prec, int full, int* blocks_per_cu, int* cus) {
+int persistent_grid(int prec, int full, int nvt, int* blocks_per_cu, int* cus) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
   int nb = 0;
-  hipError_t e;
-  if (prec == 1)
-    e = full ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<1, true>, WG, 0)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<1, false>, WG, 0);
-  else
-    e = full ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<0, true>, WG, 0)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<0, false>, WG, 0);
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_fn(prec, full, nvt), WG, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   *blocks_per_cu = nb;
   *cus = prop.multiProcessorCount;
   return 0;
 }
 
-int launch_persistent(const LaunchArgs& la, int prec, int full, int grid, void* stream) {
-  if (prec == 1) {
-    if (full) hipLaunchKernelGGL((persistent_kernel<1, true>), dim3(grid), dim3(WG), 0, S_(stream), la);
-    else hipLaunchKernelGGL((persistent_kernel<1, false>), dim3(grid), dim3(WG), 0, S_(stream), la);
-  } else {
-    if (full) hipLaunchKernelGGL((persistent_kernel<0, true>), dim3(grid), dim3(WG), 0, S_(stream), la);
-    else hipLaunchKernelGGL((persistent_kernel<0, false>), dim3(grid), dim3(WG), 0, S_(stream), la);
-  }
+int launch_persistent(const LaunchArgs& la, int prec, int full, int nvt, int grid, void* stream) {
+  hipLaunchKernelGGL(persistent_fn(prec, full, nvt), dim3(grid), dim3(WG), 0, S_(stream), la);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -123,6 +123,9 @@ static int make_geom(const double box[3], int slices, double rc, double dt, int 
   if ((double)fhi < hi) fhi = std::nextafter(fhi, 1e30f);
   g->rc2_lo_f = flo;
   g->rc2_hi_f = fhi;
+  // pre-filter threshold, 2^-10 above the band: covers the rounding of any FP32
+  // evaluation order of r2 many times over
+  g->rc2_pre_f = (float)(hi * (1.0 + std::ldexp(1.0, -10)));
   g->rc2_f = (float)g->rc2;
   g->uc_f = (float)g->uc;
   g->cps = (int)cps;
@@ -234,6 +237,7 @@ struct SimBuffers {
   uint32_t* nin[2] = {nullptr, nullptr};
   uint32_t* cntA = nullptr;
   uint32_t* cntF = nullptr;
+  uint32_t* cntK = nullptr;
   uint32_t* err = nullptr;
   uint32_t* abort = nullptr;
   unsigned long long* migcum = nullptr;
@@ -250,6 +254,7 @@ struct SimBuffers {
     }
     if ((rc = dalloc(&cntA, (size_t)g.S))) return rc;
     if ((rc = dalloc(&cntF, (size_t)g.S))) return rc;
+    if ((rc = dalloc(&cntK, (size_t)g.S))) return rc;
     if ((rc = dalloc(&err, 1))) return rc;
     if ((rc = dalloc(&abort, 1))) return rc;
     if ((rc = dalloc(&migcum, (size_t)2 * g.S))) return rc;
@@ -266,6 +271,7 @@ struct SimBuffers {
     }
     dfree(cntA);
     dfree(cntF);
+    dfree(cntK);
     dfree(err);
     dfree(abort);
     dfree(migcum);
@@ -349,6 +355,7 @@ struct md_sim {
   int64_t grid_override = 0;
   int64_t fail_at = -1;
   int64_t max_steps_per_launch = 4096;
+  double thermo_T = 0.0;  // velocity-scaling thermostat target (0: off)
   bool trace_on = false;
   std::vector<TraceRec> trace;
   TraceRec* d_trace = nullptr;
@@ -369,6 +376,9 @@ struct md_sim {
   size_t epart_cap = 0;
   uint32_t* d_miglog = nullptr;
   size_t miglog_cap = 0;
+  double* d_fbuf = nullptr;   // thermostat: forces between the force and integrate items
+  double* d_kpart = nullptr;  // thermostat: per-item kinetic energy and atom count
+  size_t kpart_cap = 0;
 };
 
 static int device_ready() {
@@ -399,7 +409,9 @@ static void free_launch_scratch(md_sim* s) {
   dfree(s->d_epart);
   dfree(s->d_miglog);
   dfree(s->d_trace);
-  s->epart_cap = s->miglog_cap = s->trace_cap = 0;
+  dfree(s->d_fbuf);
+  dfree(s->d_kpart);
+  s->epart_cap = s->miglog_cap = s->trace_cap = s->kpart_cap = 0;
 }
 
 extern "C" void md_free(md_sim* s) {
@@ -441,6 +453,14 @@ extern "C" int md_set_stream(md_sim* s, void* hip_stream) {
   if (!s) return fail(MD_EINVAL, "sim is NULL");
   HIPCHK(hipStreamSynchronize(s->stream));
   s->stream = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : s->own_stream;
+  return MD_OK;
+}
+
+extern "C" int md_set_thermostat(md_sim* s, double temperature) {
+  if (!s) return fail(MD_EINVAL, "sim is NULL");
+  if (!std::isfinite(temperature) || temperature < 0.0)
+    return fail(MD_EINVAL, "thermostat temperature must be finite and >= 0");
+  s->thermo_T = temperature;
   return MD_OK;
 }
 
@@ -607,10 +627,10 @@ extern "C" int md_load(md_sim* s, int64_t n, const double* pos, const double* ve
 // launch; tickets are dealt round by round (round k holds step k of every run that
 // still has steps), so a small run is never starved by a large one.
 // ---------------------------------------------------------------------------
-static int grid_size(int prec, int full, int64_t override_) {
+static int grid_size(int prec, int full, int nvt, int64_t override_) {
   if (override_ > 0) return (int)override_;
   int bpc = 1, cus = 1;
-  if (persistent_grid(prec, full, &bpc, &cus)) return 256;
+  if (persistent_grid(prec, full, nvt, &bpc, &cus)) return 256;
   return bpc * cus;
 }
 
@@ -680,6 +700,22 @@ static int prepare_run(md_sim* s, int64_t k_steps, hipStream_t st, RunArgs* ra, 
   ra->count = s->count_pairs ? 1 : 0;
   ra->fail_at = s->fail_at;
   ra->ips = 2 * g.S * s->nch;
+  if (s->thermo_T > 0.0) {
+    if (s->order_kind != MD_ORDER_DATAFLOW)
+      return fail(MD_EINVAL, "the thermostat runs with the dataflow scheduler only");
+    if (!s->d_fbuf && (rc = dalloc(&s->d_fbuf, (size_t)g.ncell * 3 * CELL_CAP))) return rc;
+    const size_t kp = (size_t)g.S * s->nch * 2;
+    if (kp > s->kpart_cap) {
+      dfree(s->d_kpart);
+      if ((rc = dalloc(&s->d_kpart, kp))) return rc;
+      s->kpart_cap = kp;
+    }
+    ra->thermo_T = s->thermo_T;
+    ra->fbuf = s->d_fbuf;
+    ra->kpart = s->d_kpart;
+    ra->cntK = s->b.cntK;
+    ra->ips = 3 * g.S * s->nch;
+  }
   *nsample_out = nsample;
   *first_j_out = first_j;
   return MD_OK;
@@ -770,7 +806,7 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   HIPCHK(hipMemcpy(ls.d_round_active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice));
   const int mode = sims[idx[0]]->order_kind == MD_ORDER_DATAFLOW ? 0 : 1;
   const size_t total = (size_t)rb[(size_t)nrounds];
-  if (nrounds >= (1 << 20)) return fail(MD_EINVAL, "too many steps in one launch");
+  if (nrounds >= (1 << 19)) return fail(MD_EINVAL, "too many steps in one launch");
   if (mode == 0) {
     if (total > ls.q_cap) {
       dfree(ls.d_q);
@@ -810,17 +846,19 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
     la.trace = trace_owner->d_trace;
   }
   if (launch_init(la, std::max<long long>(prefill, max_slices), st)) return fail(MD_EHIP, "init failed");
-  int full = 0;
-  for (size_t q = 0; q < R; q++)
+  int full = 0, nvt = 0;
+  for (size_t q = 0; q < R; q++) {
     if (ra[q].count || nsample[idx[q]] > 0 || ra[q].fail_at >= 0) full = 1;
-  const int grid = grid_size(prec, full, grid_override);
+    if (ra[q].thermo_T > 0.0) nvt = 1;
+  }
+  const int grid = grid_size(prec, full, nvt, grid_override);
   if (last_grid) *last_grid = grid;
   if (!ls.ev[0]) {
     HIPCHK(hipEventCreate(&ls.ev[0]));
     HIPCHK(hipEventCreate(&ls.ev[1]));
   }
   HIPCHK(hipEventRecord(ls.ev[0], st));
-  if (launch_persistent(la, prec, full, grid, st)) return fail(MD_EHIP, "persistent launch failed");
+  if (launch_persistent(la, prec, full, nvt, grid, st)) return fail(MD_EHIP, "persistent launch failed");
   HIPCHK(hipEventRecord(ls.ev[1], st));
   HIPCHK(hipStreamSynchronize(st));
   if (kernel_seconds) {

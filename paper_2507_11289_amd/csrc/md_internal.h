@@ -38,6 +38,7 @@ struct DGeom {
   float rc2_f;     // rc^2 in FP32
   float rc2_lo_f;  // FP32 pairs with r2 <= rc2_lo_f are in range for certain
   float rc2_hi_f;  // FP32 pairs with r2 >  rc2_hi_f are out of range for certain
+  float rc2_pre_f; // pre-filter: every pair with FP32 r2 <= rc2_hi_f has r2 < rc2_pre_f
   float uc_f;
   int S;           // slices
   int ncx;         // cell layers per slice
@@ -69,7 +70,11 @@ struct RunArgs {
   int every;                    // energy sampling interval (0 = none)
   int count;                    // count candidates / in-range partners
   long long fail_at;            // debug fault injection step (-1 off)
-  int ips;                      // items per step = 2 * S * nch
+  int ips;                      // items per step: 2 * S * nch (3 * S * nch with the thermostat)
+  double thermo_T;              // velocity-scaling thermostat target temperature (0: off)
+  double* fbuf;                 // thermostat: F(t) per slot of the step's cells [ncell][3][64]
+  double* kpart;                // thermostat: [S][nch][2] kinetic energy and atoms of v(t)
+  uint32_t* cntK;               // thermostat: per slice, force items completed in this launch
 };
 
 struct TraceRec {
@@ -103,8 +108,8 @@ int launch_load_scatter(const DGeom& g, const double* pos, const double* vel, lo
 int launch_sort_cells(const DGeom& g, unsigned char* cells, uint32_t* ncnt, uint32_t* err,
                       void* stream);
 int launch_init(const LaunchArgs& la, long long work, void* stream);
-int persistent_grid(int prec, int full, int* blocks_per_cu, int* cus);
-int launch_persistent(const LaunchArgs& la, int prec, int full, int grid, void* stream);
+int persistent_grid(int prec, int full, int nvt, int* blocks_per_cu, int* cus);
+int launch_persistent(const LaunchArgs& la, int prec, int full, int nvt, int grid, void* stream);
 int launch_sync(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int first,
                 double* out_pos, double* out_vel, double* out_force, double* epart,
                 uint32_t* err, void* stream);

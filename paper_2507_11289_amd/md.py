@@ -81,6 +81,7 @@ _SIGS = {
     "md_get_stats": ([C.c_void_p, C.POINTER(md_stats)], C.c_int),
     "md_get_trace": ([C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
     "md_set_option": ([C.c_void_p, C.c_int, C.c_int64], C.c_int),
+    "md_set_thermostat": ([C.c_void_p, C.c_double], C.c_int),
     "md_set_stream": ([C.c_void_p, C.c_void_p], C.c_int),
     "md_free": ([C.c_void_p], None),
     "md_strerror": ([C.c_int], C.c_char_p),
@@ -248,6 +249,10 @@ class Sim:
 
     def set_option(self, key: int, value: int):
         _check(lib().md_set_option(self._h, int(key), int(value)), "md_set_option")
+
+    def set_thermostat(self, temperature: float):
+        """Per-slice velocity-scaling thermostat at `temperature` (0 switches it off)."""
+        _check(lib().md_set_thermostat(self._h, float(temperature)), "md_set_thermostat")
 
     def set_stream(self, stream_handle):
         _check(lib().md_set_stream(self._h, C.c_void_p(stream_handle)), "md_set_stream")
