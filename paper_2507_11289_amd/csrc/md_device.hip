@@ -51,9 +51,6 @@ __device__ __forceinline__ const uint32_t* cids(const double* b) {
   return reinterpret_cast<const uint32_t*>(b + CELL_DOUBLES);
 }
 
-__device__ __forceinline__ unsigned ld_acquire(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ unsigned ld_relaxed(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -151,6 +148,8 @@ template <> struct BlockLDS<0> {  // FP64: raw positions + tag
 
 struct ForceOut {
   double fx, fy, fz;  // force on the lane's atom (lanes < n)
+  double x[3], v[3];  // FP64 position and stored velocity of the lane's atom
+  uint32_t id;        // its id
   double uh, wh;      // half sums of pair energy / pair virial
   unsigned pc;        // in-range partners (count mode)
   int n;              // atoms in the cell (uniform per wave)
@@ -251,93 +250,164 @@ __device__ __forceinline__ void pair64(const DGeom& g, double xi, double yi, dou
   if (COUNT) a.pc += in ? 1u : 0u;
 }
 
-// Stage the block of the column (gx, gy) whose cells start at z0 (at most nb_max of
-// them, all in the column); returns the cells actually taken (capacity may shorten the
-// block).  Whole workgroup; ends with a barrier.
-template <int PREC>
-__device__ int stage_block(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int gx, int gy,
-                           int z0, int nb_max, BlockLDS<PREC>& L) {
-  const int tid = threadIdx.x;
-  __syncthreads();
-  if (tid < 64) {
-    // wave 0: neighbour cells, counts, prefix, capacity
-    const int m = tid;
-    const int lay = m / 9, r = m % 9;
-    int cnt = 0, nc = 0;
-    if (m < BCELLS && lay < nb_max + 2) {
-      int nx = gx + r / 3 - 1, ny = gy + r % 3 - 1, nz = z0 - 1 + lay;
-      nx += nx < 0 ? g.G[0] : (nx >= g.G[0] ? -g.G[0] : 0);
-      ny += ny < 0 ? g.G[1] : (ny >= g.G[1] ? -g.G[1] : 0);
-      nz += nz < 0 ? g.G[2] : (nz >= g.G[2] ? -g.G[2] : 0);
-      nc = global_cell(g, nx, ny, nz);
-      cnt = (int)ncnt[nc];
-    }
-    int incl = cnt;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int v = __shfl_up(incl, off);
-      if (m >= off) incl += v;
-    }
-    if (m < BCELLS) {
-      L.h.nb_cell[m] = nc;
-      L.h.cnt[m] = cnt;
-      L.h.pre[m] = incl - cnt;
-    }
-    if (m == BCELLS - 1) L.h.pre[BCELLS] = incl;
-    // largest nb with its 9 (nb + 2) cells within capacity (nb = 1 always fits)
-    int nb = nb_max;
-    while (nb > 1 && __shfl(incl, 9 * (nb + 2) - 1) > CAPB) nb--;
-    if (m == 0) {
-      L.h.nb = nb;
-      L.h.wrap_col = gx == 0 || gx == g.G[0] - 1 || gy == 0 || gy == g.G[1] - 1;
-    }
-    if (m < BLAYERS) {
-      const int nz = z0 - 1 + m;
-      L.h.wrap_layer[m] = nz < 0 || nz >= g.G[2];
-    }
+// Staging of the block of the column (gx, gy) whose cells start at z0 (at most nb_max
+// of them, all in the column), in two halves:
+//   stage_issue: every wave loads the atom counts of the block's cells (lane m: staged
+//     cell m) -- issued one block ahead, so they arrive while the previous block is
+//     integrated;
+//   stage_commit: prefix of the counts, capacity check, header; then every thread takes
+//     up to SROUNDS entries of the compact staged list (entries tid, tid + WG, ...),
+//     finds their cell by a binary search over the prefix, and loads all of them at
+//     once (one memory round trip for the whole block), then writes them into LDS.
+// ---------------------------------------------------------------------------
+constexpr int SROUNDS = 4;  // staged entries per thread and memory round trip
+
+// threadIdx.x behind an empty asm: index arithmetic derived from it stays where it is
+// used instead of being hoisted out of the block loop and held in registers through the
+// pair loop.
+__device__ __forceinline__ int opaque_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+struct StageRegs {
+  int gx, gy, z0, nb_max;
+  int nc, cnt;  // lane m < 9 (nb_max + 2): global cell and atom count of staged cell m
+};
+
+__device__ __forceinline__ void staged_cell_xyz(int gx, int gy, int z0, int m, int& nx, int& ny, int& nz) {
+  const int lay = m / 9, r = m % 9;
+  nx = gx + r / 3 - 1;
+  ny = gy + r % 3 - 1;
+  nz = z0 - 1 + lay;
+}
+
+__device__ __forceinline__ void stage_issue(const DGeom& g, const uint32_t* ncnt, int gx, int gy, int z0,
+                                            int nb_max, StageRegs& R) {
+  const int lane = __lane_id();
+  R.gx = gx;
+  R.gy = gy;
+  R.z0 = z0;
+  R.nb_max = nb_max;
+  const int ncs = 9 * (nb_max + 2);
+  int nc = 0;
+  if (lane < ncs) {
+    int nx, ny, nz;
+    staged_cell_xyz(gx, gy, z0, lane, nx, ny, nz);
+    nx += nx < 0 ? g.G[0] : (nx >= g.G[0] ? -g.G[0] : 0);
+    ny += ny < 0 ? g.G[1] : (ny >= g.G[1] ? -g.G[1] : 0);
+    nz += nz < 0 ? g.G[2] : (nz >= g.G[2] ? -g.G[2] : 0);
+    nc = global_cell(g, nx, ny, nz);
   }
-  __syncthreads();
-  const int nb = L.h.nb;
-  // stage: 4 threads per staged cell, slots sub, sub + 4, ...
-  const int ms = tid >> 2, sub = tid & 3;
-  // FP32 origin: the column corner at the start of z0's aligned group of BZ cells, so a
-  // pair's FP32 arithmetic depends on the cell only, not on how cells form blocks
-  const double ox = gx * g.l[0], oy = gy * g.l[1], oz = (z0 - z0 % BZ) * g.l[2];
+  R.nc = nc;
+  R.cnt = lane < ncs ? (int)ncnt[nc] : 0;
+}
+
+template <int PREC>
+__device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, BlockLDS<PREC>& L, int m, int k,
+                                          int p, double x, double y, double z) {
   if constexpr (PREC == 1) {
+    // FP32 origin: the column corner at the start of z0's aligned group of BZ cells, so
+    // a pair's FP32 arithmetic depends on the cell only, not on how cells form blocks
+    const double ox = __dmul_rn((double)R.gx, g.l[0]), oy = __dmul_rn((double)R.gy, g.l[1]),
+                 oz = __dmul_rn((double)(R.z0 - R.z0 % BZ), g.l[2]);
+    int nx, ny, nz;
+    staged_cell_xyz(R.gx, R.gy, R.z0, m, nx, ny, nz);
+    const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
+    const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
+    const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
+    L.q[p] = make_float4((float)__dsub_rn(__dadd_rn(x, shx), ox), (float)__dsub_rn(__dadd_rn(y, shy), oy),
+                         (float)__dsub_rn(__dadd_rn(z, shz), oz),
+                         __uint_as_float(((unsigned)m << 6) | (unsigned)k));
+  } else {
+    L.t.x[p] = x;
+    L.t.y[p] = y;
+    L.t.z[p] = z;
+    L.tag[p] = (uint16_t)((m << 6) | k);
+  }
+}
+
+// Returns the cells actually taken (capacity may shorten the block).  Whole
+// workgroup; the LDS must be free on entry; ends with a barrier.
+template <int PREC>
+__device__ int stage_commit(const DGeom& g, const unsigned char* cells, const StageRegs& R, BlockLDS<PREC>& L) {
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  int incl = R.cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  const int pre = incl - R.cnt;
+  // largest nb with its 9 (nb + 2) cells within capacity (nb = 1 always fits)
+  int nb = R.nb_max;
+  while (nb > 1 && __shfl(incl, 9 * (nb + 2) - 1) > CAPB) nb--;
+  const int nst = 9 * (nb + 2);
+  const int stot = __shfl(incl, nst - 1);
+  if (w == 0) {
+    if (lane < BCELLS) {
+      L.h.nb_cell[lane] = R.nc;
+      L.h.cnt[lane] = R.cnt;
+      L.h.pre[lane] = pre;
+    }
+    if (lane == BCELLS - 1) L.h.pre[BCELLS] = incl;
+    if (lane == 0) {
+      L.h.nb = nb;
+      L.h.wrap_col = R.gx == 0 || R.gx == g.G[0] - 1 || R.gy == 0 || R.gy == g.G[1] - 1;
+    }
+    if (lane < BLAYERS) {
+      const int nz = R.z0 - 1 + lane;
+      L.h.wrap_layer[lane] = nz < 0 || nz >= g.G[2];
+    }
     // far sentinels after the last staged atom: a pair-loop read past the end of the
     // list finds no partner in range
-    if (tid < QPAD) L.q[L.h.pre[9 * (nb + 2)] + tid] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
-  }
-  for (int mb = 0; mb < 9 * (nb + 2); mb += WG / 4) {
-    const int m = mb + ms;
-    if (m >= 9 * (nb + 2)) break;
-    const int n = L.h.cnt[m];
-    if (n == 0) continue;
-    const double* jb = cblk(cells, L.h.nb_cell[m]);
-    const int p = L.h.pre[m];
-    double shx = 0.0, shy = 0.0, shz = 0.0;
     if constexpr (PREC == 1) {
-      const int lay = m / 9, r = m % 9;
-      const int nx = gx + r / 3 - 1, ny = gy + r % 3 - 1, nz = z0 - 1 + lay;
-      shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
-      shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
-      shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
+      if (lane < QPAD) L.q[stot + lane] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
     }
-    for (int k = sub; k < n; k += 4) {
-      const double x = jb[k], y = jb[CELL_CAP + k], z = jb[2 * CELL_CAP + k];
-      if constexpr (PREC == 1) {
-        L.q[p + k] = make_float4((float)((x + shx) - ox), (float)((y + shy) - oy), (float)((z + shz) - oz),
-                                 __uint_as_float(((unsigned)m << 6) | (unsigned)k));
-      } else {
-        L.t.x[p + k] = x;
-        L.t.y[p + k] = y;
-        L.t.z[p + k] = z;
-        L.tag[p + k] = (uint16_t)((m << 6) | k);
+  }
+  const int tid = opaque_tid();
+  for (int base = 0; base < stot; base += WG * SROUNDS) {
+    int mm[SROUNDS], kk[SROUNDS];
+    double x[SROUNDS], y[SROUNDS], z[SROUNDS];
+#pragma unroll
+    for (int r = 0; r < SROUNDS; r++) {
+      const int f = base + tid + WG * r;
+      // cell of entry f: the first staged cell whose inclusive prefix exceeds f
+      int m = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1)
+        if (__shfl(incl, m + step - 1) <= f) m += step;
+      const int k = f - __shfl(pre, m & 63);
+      const int cm = __shfl(R.nc, m & 63);
+      mm[r] = m;
+      kk[r] = k;
+      if (f < stot) {
+        const double* jb = cblk(cells, cm);
+        x[r] = jb[k];
+        y[r] = jb[CELL_CAP + k];
+        z[r] = jb[2 * CELL_CAP + k];
       }
+    }
+#pragma unroll
+    for (int r = 0; r < SROUNDS; r++) {
+      const int f = base + tid + WG * r;
+      if (f < stot) stage_put<PREC>(g, R, L, mm[r], kk[r], f, x[r], y[r], z[r]);
     }
   }
   __syncthreads();
   return nb;
+}
+
+// Both halves at once (the synchronous read-back path).  Whole workgroup.
+template <int PREC>
+__device__ int stage_block(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int gx, int gy,
+                           int z0, int nb_max, BlockLDS<PREC>& L) {
+  StageRegs R;
+  stage_issue(g, ncnt, gx, gy, z0, nb_max, R);
+  __syncthreads();
+  return stage_commit<PREC>(g, cells, R, L);
 }
 
 // Pair forces of every atom of the cell of this wave in the staged block
@@ -526,23 +596,51 @@ __device__ void block_force(const DGeom& g, const unsigned char* cells, int gx, 
 }
 
 // Walk the cells [b, e) of one slice (local indices, z fastest) block by block; fn(o)
-// runs on every wave after each block's forces.  Whole workgroup.
-template <int PREC, bool ENERGY, bool COUNT, class Fn>
+// runs on every wave after each block's forces, while the counts of the next block are
+// in flight.  With OWN, the position, velocity and id of the wave's own atoms are loaded
+// right after staging and arrive during the pair loop.  Whole workgroup.
+template <int PREC, bool ENERGY, bool COUNT, bool OWN, class Fn>
 __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int slice, int b,
                            int e, BlockLDS<PREC>& L, Fn&& fn) {
-  int x = b;
-  while (x < e) {
-    const int gz = x % g.G[2];
-    const int t = x / g.G[2];
+  if (b >= e) return;
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  // blocks stay within the column and within one aligned group of BZ cells
+  auto issue = [&](int xs, StageRegs& R) {
+    const int gz = xs % g.G[2];
+    const int t = xs / g.G[2];
     const int gy = t % g.G[1];
     const int gx = slice * g.ncx + t / g.G[1];
-    // blocks stay within the column and within one aligned group of BZ cells
-    const int nb_max = min(min(BZ - gz % BZ, e - x), g.G[2] - gz);
-    const int nb = stage_block<PREC>(g, cells, ncnt, gx, gy, gz, nb_max, L);
+    const int nb_max = min(min(BZ - gz % BZ, e - xs), g.G[2] - gz);
+    stage_issue(g, ncnt, gx, gy, gz, nb_max, R);
+  };
+  StageRegs R;
+  int x = b;
+  issue(x, R);
+  while (true) {
+    __syncthreads();  // every wave is done with the previous block's LDS
+    const int nb = stage_commit<PREC>(g, cells, R, L);
     ForceOut o;
-    block_force<PREC, ENERGY, COUNT>(g, cells, gx, gy, gz, L, o);
-    fn(o);
+    if (OWN) {
+      const int ci = 9 * (w + 1) + 4;
+      const int n_own = w < nb ? __shfl(R.cnt, ci) : 0;
+      const int c_own = __shfl(R.nc, ci);
+      if (lane < n_own) {
+        const double* ib = cblk(cells, c_own);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+          o.x[d] = ib[d * CELL_CAP + lane];
+          o.v[d] = ib[(3 + d) * CELL_CAP + lane];
+        }
+        o.id = cids(ib)[lane];
+      }
+    }
+    block_force<PREC, ENERGY, COUNT>(g, cells, R.gx, R.gy, R.z0, L, o);
     x += nb;
+    const bool more = x < e;
+    if (more) issue(x, R);
+    fn(o);
+    if (!more) break;
   }
 }
 
@@ -586,7 +684,6 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first
     return;
   }
   const bool own = lane < o.n;
-  const double* ib = cblk(ra.cells[src], c);
   const int s_old = c / g.cps;
   double xn[3] = {0, 0, 0}, vh[3] = {0, 0, 0};
   uint32_t id = 0;
@@ -598,7 +695,7 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first
     double vf[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-      const double v = ib[(3 + d) * CELL_CAP + lane];
+      const double v = o.v[d];
       vf[d] = first ? v : __dadd_rn(v, __dmul_rn(g.hdt, F[d]));
       if (SCALE) vf[d] = __dmul_rn(lam, vf[d]);
     }
@@ -616,13 +713,13 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first
 #pragma unroll
     for (int d = 0; d < 3; d++) {
       vh[d] = __dadd_rn(vf[d], __dmul_rn(g.hdt, F[d]));
-      const double x = __dadd_rn(ib[d * CELL_CAP + lane], __dmul_rn(g.dt, vh[d]));
+      const double x = __dadd_rn(o.x[d], __dmul_rn(g.dt, vh[d]));
       xn[d] = wrap1(x, g.L[d]);
       if (!isfinite(xn[d]) || !isfinite(vh[d]) || !(xn[d] >= 0.0) || xn[d] > g.L[d])
         bad |= ERR_NONFINITE;
       gc[d] = coord_cell(xn[d], g.inv_l[d], g.G[d]);
     }
-    id = cids(ib)[lane];
+    id = o.id;
     dest = global_cell(g, gc[0], gc[1], gc[2]);
     const int s_new = gc[0] / g.ncx;
     const int delta = (s_new - s_old + g.S) % g.S;
@@ -668,12 +765,11 @@ __device__ void p2_force_tail(const RunArgs& ra, const ForceOut& o, int src, int
   const int lane = __lane_id();
   const int c = o.c;
   if (c < 0 || lane >= o.n) return;
-  const double* ib = cblk(ra.cells[src], c);
   const double F[3] = {o.fx, o.fy, o.fz};
   double vf[3];
 #pragma unroll
   for (int d = 0; d < 3; d++) {
-    const double v = ib[(3 + d) * CELL_CAP + lane];
+    const double v = o.v[d];
     vf[d] = first ? v : __dadd_rn(v, __dmul_rn(g.hdt, F[d]));
   }
   const double ke =
@@ -791,12 +887,14 @@ __device__ __forceinline__ void dec_item(unsigned long long v, Item& it) {
   it.chunk = (int)(v & 0xfffull);
 }
 
+// Polls with relaxed loads (an acquire per poll would invalidate this XCD's L2 each
+// time); the caller issues one acquire fence once the counters are reached.
 __device__ bool wait_counters(const LaunchArgs& la, const uint32_t* cnt, int S, int s, unsigned need,
                               uint32_t* err, uint32_t* abort_flag) {
   const long long t_begin = wall_clock64();
   const int nb[3] = {(s + S - 1) % S, s, (s + 1) % S};
   for (int q = 0; q < 3; q++) {
-    while (ld_acquire(cnt + nb[q]) < need) {
+    while (ld_relaxed(cnt + nb[q]) < need) {
       if (ld_relaxed(abort_flag)) return false;
       if (wall_clock64() - t_begin > la.watchdog_ticks) {
         raise_error(err, abort_flag, ERR_WATCHDOG);
@@ -821,7 +919,7 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L
   const int e = (int)((long long)ra.g.cps * (it.chunk + 1) / ra.nch);
   ItemAcc acc;
   acc_zero(acc);
-  for_blocks<PREC, ENERGY, COUNT>(ra.g, ra.cells[src], ra.ncnt[src], it.slice, b, e, L, [&](const ForceOut& o) {
+  for_blocks<PREC, ENERGY, COUNT, true>(ra.g, ra.cells[src], ra.ncnt[src], it.slice, b, e, L, [&](const ForceOut& o) {
     if (NVT) p2_force_tail<ENERGY, COUNT>(ra, o, src, first, acc);
     else p2_tail<ENERGY, COUNT, false>(ra, o, src, first, acc, abort_flag, 1.0);
   });
@@ -943,6 +1041,13 @@ __device__ void run_p2b_item(const RunArgs& ra, const Item& it, double* s_lam, u
       o.fx = fb[lane];
       o.fy = fb[CELL_CAP + lane];
       o.fz = fb[2 * CELL_CAP + lane];
+      const double* ib = cblk(ra.cells[src], c);
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        o.x[d] = ib[d * CELL_CAP + lane];
+        o.v[d] = ib[(3 + d) * CELL_CAP + lane];
+      }
+      o.id = cids(ib)[lane];
     }
     p2_tail<false, false, true>(ra, o, src, first, acc, abort_flag, lam);
   }
@@ -1004,20 +1109,24 @@ __device__ void run_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& ws, 
   }
 }
 
-// Dataflow completion: count this item towards its dependents; the count that completes
-// a dependency set appends the dependent items (all chunks) to the queue.
+// Dataflow completion (thread 0, after the item's release fence): count this item
+// towards its dependents with relaxed increments; the count that completes a dependency
+// set acquires (every counted item released before its increment), releases, and
+// appends the dependent items (all chunks) to the queue.
 __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const Item& it) {
   const int S = ra.g.S;
   const bool nvt = ra.thermo_T > 0.0;
   if (nvt && it.phase == 0) {
     // thermostat: the slice's integrate items wait for all of its force items
     const unsigned needk = (unsigned)ra.nch * (unsigned)(it.k + 1);
-    const unsigned old = __hip_atomic_fetch_add(ra.cntK + it.slice, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned old = __hip_atomic_fetch_add(ra.cntK + it.slice, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old + 1u != needk) return;
+    // the completing count: see every counted item's results, then publish the pushes
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
     const unsigned long long base =
         __hip_atomic_fetch_add(la.q_tail, (unsigned long long)ra.nch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int ch = 0; ch < ra.nch; ch++)
-      __hip_atomic_store(la.q + base + ch, enc_item(it.run, it.k, 2, it.slice, ch), __ATOMIC_RELEASE,
+      __hip_atomic_store(la.q + base + ch, enc_item(it.run, it.k, 2, it.slice, ch), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
@@ -1028,8 +1137,10 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
   uint32_t* cnt = update ? ra.cntF : ra.cntA;
   for (int d = -1; d <= 1; d++) {
     const int j = (it.slice + d + S) % S;
-    const unsigned old = __hip_atomic_fetch_add(cnt + j, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned old = __hip_atomic_fetch_add(cnt + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old + 1u != need) continue;
+    // the completing count: see every counted item's results, then publish the pushes
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
     int phase, k;
     if (update) {
       phase = 1;  // finalise of step k+1
@@ -1042,7 +1153,7 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
     const unsigned long long base =
         __hip_atomic_fetch_add(la.q_tail, (unsigned long long)ra.nch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int ch = 0; ch < ra.nch; ch++)
-      __hip_atomic_store(la.q + base + ch, enc_item(it.run, k, phase, j, ch), __ATOMIC_RELEASE,
+      __hip_atomic_store(la.q + base + ch, enc_item(it.run, k, phase, j, ch), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -1071,7 +1182,8 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
           // dataflow: wait for slot T to be filled
           const long long t_begin = wall_clock64();
           unsigned long long v;
-          while (!((v = __hip_atomic_load(la.q + T, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) >> 63)) {
+          // relaxed polling; the acquire fence follows once the item is known
+          while (!((v = __hip_atomic_load(la.q + T, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 63)) {
             if (ld_relaxed(la.launch_err)) break;
             if (wall_clock64() - t_begin > la.watchdog_ticks) {
               raise_error(la.launch_err, nullptr, ERR_WATCHDOG);
@@ -1120,6 +1232,8 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
         const unsigned need = (unsigned)(it.k + 1) * (unsigned)ra.nch;
         ok = wait_counters(la, it.phase == 0 ? ra.cntA : ra.cntF, ra.g.S, it.slice, need, ra.err, ra.abort);
       }
+      // one acquire for the workgroup: the barrier below orders every wave after it
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       s_ok = ok;
       if (la.trace) {
         TraceRec& tr = la.trace[s_ticket];
@@ -1134,20 +1248,20 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
     }
     __syncthreads();
     const int ok = s_ok;
-    if (ok) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      run_item<PREC, FULL, NVT>(ra, it, ws, s_red, s_cnt);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (ok) run_item<PREC, FULL, NVT>(ra, it, ws, s_red, s_cnt);
+    // every wave's stores have reached the L2 before the barrier (the barrier itself
+    // does not wait for them); thread 0's release then covers the whole workgroup
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (la.trace) la.trace[s_ticket].t_done = wall_clock64();
       if (la.mode == 0) {
         // an aborted run still completes its items (without work) so the queue drains
         complete_dataflow(la, ra, it);
       } else if (ok) {
         uint32_t* cnt = it.phase == 0 ? ra.cntF : ra.cntA;
-        __hip_atomic_fetch_add(cnt + it.slice, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(cnt + it.slice, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     __syncthreads();
@@ -1265,7 +1379,7 @@ __global__ __launch_bounds__(WG) void sync_kernel(DGeom g, const unsigned char* 
   const int slice = blockIdx.x / per_slice;
   const int b = (blockIdx.x % per_slice) * SYNC_CELLS;
   const int e = min(g.cps, b + SYNC_CELLS);
-  for_blocks<PREC, true, false>(g, cells, ncnt, slice, b, e, L, [&](const ForceOut& o) {
+  for_blocks<PREC, true, false, false>(g, cells, ncnt, slice, b, e, L, [&](const ForceOut& o) {
     if (o.c >= 0 && lane < o.n) {
       const double* ib = cblk(cells, o.c);
       const uint32_t id = cids(ib)[lane];
