@@ -32,17 +32,17 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_11289_amd", "csrc", "md_device.hi
 
 # HBM traffic of one 100-step launch of the FP32-force persistent kernel on lj_fluid_4m,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) and the same
-# counters on a plain device copy of known size (profiles/persistent_kernel_lj_fluid_4m_fp32.md).
+# counters on a plain device copy of known size (profiles/persistent_f32_lean_lj_fluid_4m.md).
 # Valid only for the kernel source they were taken on (sha256 below); otherwise null.
 TRAFFIC = {
-    "source_sha256": "76b7b4a94cd4b6ca97789427c08a513b58c4788124252db690685957cc0680ce",
+    "source_sha256": "401a617f323778d5834b05499171394b2690350e9521450de5a7b49a0c57e329",
     "workload": "lj_fluid_4m",
     "steps_per_launch": 100,
-    "fetch_kib_per_launch": 68014325,      # FETCH_SIZE, mean of 3 dispatches
-    "write_kib_per_launch": 26110813,      # WRITE_SIZE, mean of 3 dispatches
+    "fetch_kib_per_launch": 69638441,      # FETCH_SIZE, mean of 3 dispatches
+    "write_kib_per_launch": 26474358,      # WRITE_SIZE, mean of 3 dispatches
     "copy_fetch_factor": 0.50001,          # FETCH_SIZE KiB / KiB really read by a 1 GiB copy
     "copy_write_factor": 1.00000,          # WRITE_SIZE KiB / KiB really written by it
-    "hbm_bytes_per_launch": 1.6603e+11,
+    "hbm_bytes_per_launch": 1.6973e+11,
 }
 
 

@@ -304,14 +304,21 @@ __device__ __forceinline__ void stage_issue(const DGeom& g, const uint32_t* ncnt
   R.cnt = lane < ncs ? (int)ncnt[nc] : 0;
 }
 
+// wrap: some staged cell of the block is a periodic image (its coordinates are shifted
+// by a box length); without it the shift is 0 and x + 0 = x exactly.
 template <int PREC>
 __device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, BlockLDS<PREC>& L, int m, int k,
-                                          int p, double x, double y, double z) {
+                                          int p, double x, double y, double z, bool wrap) {
   if constexpr (PREC == 1) {
     // FP32 origin: the column corner at the start of z0's aligned group of BZ cells, so
     // a pair's FP32 arithmetic depends on the cell only, not on how cells form blocks
     const double ox = __dmul_rn((double)R.gx, g.l[0]), oy = __dmul_rn((double)R.gy, g.l[1]),
                  oz = __dmul_rn((double)(R.z0 - R.z0 % BZ), g.l[2]);
+    if (!wrap) {
+      L.q[p] = make_float4((float)__dsub_rn(x, ox), (float)__dsub_rn(y, oy), (float)__dsub_rn(z, oz),
+                           __uint_as_float(((unsigned)m << 6) | (unsigned)k));
+      return;
+    }
     int nx, ny, nz;
     staged_cell_xyz(R.gx, R.gy, R.z0, m, nx, ny, nz);
     const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
@@ -367,6 +374,8 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
       if (lane < QPAD) L.q[stot + lane] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
     }
   }
+  const bool wrap = R.gx == 0 || R.gx == g.G[0] - 1 || R.gy == 0 || R.gy == g.G[1] - 1 || R.z0 == 0 ||
+                    R.z0 + nb >= g.G[2];
   const int tid = opaque_tid();
   for (int base = 0; base < stot; base += WG * SROUNDS) {
     int mm[SROUNDS], kk[SROUNDS];
@@ -393,7 +402,7 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
 #pragma unroll
     for (int r = 0; r < SROUNDS; r++) {
       const int f = base + tid + WG * r;
-      if (f < stot) stage_put<PREC>(g, R, L, mm[r], kk[r], f, x[r], y[r], z[r]);
+      if (f < stot) stage_put<PREC>(g, R, L, mm[r], kk[r], f, x[r], y[r], z[r], wrap);
     }
   }
   __syncthreads();
