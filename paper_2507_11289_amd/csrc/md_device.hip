@@ -553,52 +553,110 @@ __device__ void block_force(const DGeom& g, const unsigned char* cells, int gx, 
   // every wave is done with the staged positions; the same LDS now holds the partials
   __syncthreads();
   if (n_i > 0) {
-    // values per lane: force (3) and, when sampled or counted, energy, virial, count
-    constexpr int NV = (ENERGY || COUNT) ? 6 : 3;
-    double sa[NV], sb[NV];
-#pragma unroll
-    for (int v = 0; v < NV; v++) sa[v] = sb[v] = 0.0;
-    double* red = L.red[w];
-    for (int h = 0; h < 2; h++) {
-      const Acc<R>& X = h == 0 ? A : B;
+    // Forces: both atoms' group partials per lane, summed in group order (a fixed order,
+    // the same in every kernel variant), then handed to the lane of each atom.
+    if constexpr (PREC == 1) {
+      // FP32: two float4 per lane, FP32 sums
+      float4* r4 = reinterpret_cast<float4*>(L.red[w]);
+      r4[2 * lane] = make_float4((float)A.fx, (float)A.fy, (float)A.fz, (float)B.fx);
+      r4[2 * lane + 1] = make_float4((float)B.fy, (float)B.fz, 0.0f, 0.0f);
       wave_sync();
-      red[lane * NV + 0] = (double)X.fx;
-      red[lane * NV + 1] = (double)X.fy;
-      red[lane * NV + 2] = (double)X.fz;
-      if constexpr (NV == 6) {
-        red[lane * NV + 3] = X.u;
-        red[lane * NV + 4] = X.w;
-        red[lane * NV + 5] = (double)X.pc;
+      float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, s4 = 0.0f, s5 = 0.0f;
+      if (lane < P) {
+        for (int q = 0; q < G; q++) {
+          const float4 u = r4[2 * (lane + q * P)], v = r4[2 * (lane + q * P) + 1];
+          s0 += u.x;
+          s1 += u.y;
+          s2 += u.z;
+          s3 += u.w;
+          s4 += v.x;
+          s5 += v.y;
+        }
       }
       wave_sync();
       if (lane < P) {
-        double* s = h == 0 ? sa : sb;
+        r4[lane] = make_float4(s0, s1, s2, 0.0f);
+        if (lane + P < n_i) r4[lane + P] = make_float4(s3, s4, s5, 0.0f);
+      }
+      wave_sync();
+      if (lane < n_i) {
+        const float4 t = r4[lane];
+        o.fx = t.x;
+        o.fy = t.y;
+        o.fz = t.z;
+      }
+    } else {
+      // FP64: three double2 per lane
+      double2* r2 = reinterpret_cast<double2*>(L.red[w]);
+      r2[3 * lane] = make_double2((double)A.fx, (double)A.fy);
+      r2[3 * lane + 1] = make_double2((double)A.fz, (double)B.fx);
+      r2[3 * lane + 2] = make_double2((double)B.fy, (double)B.fz);
+      wave_sync();
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0;
+      if (lane < P) {
         for (int q = 0; q < G; q++) {
-          const double* r = red + (lane + q * P) * NV;
-#pragma unroll
-          for (int v = 0; v < NV; v++) s[v] += r[v];
+          const int j = 3 * (lane + q * P);
+          const double2 u = r2[j], v = r2[j + 1], t = r2[j + 2];
+          s0 += u.x;
+          s1 += u.y;
+          s2 += v.x;
+          s3 += v.y;
+          s4 += t.x;
+          s5 += t.y;
         }
       }
-    }
-    wave_sync();
-    if (lane < P) {
-#pragma unroll
-      for (int v = 0; v < NV; v++) red[lane * NV + v] = sa[v];
-      if (lane + P < n_i) {
-#pragma unroll
-        for (int v = 0; v < NV; v++) red[(lane + P) * NV + v] = sb[v];
+      wave_sync();
+      if (lane < P) {
+        r2[2 * lane] = make_double2(s0, s1);
+        r2[2 * lane + 1] = make_double2(s2, 0.0);
+        if (lane + P < n_i) {
+          r2[2 * (lane + P)] = make_double2(s3, s4);
+          r2[2 * (lane + P) + 1] = make_double2(s5, 0.0);
+        }
+      }
+      wave_sync();
+      if (lane < n_i) {
+        const double2 u = r2[2 * lane], v = r2[2 * lane + 1];
+        o.fx = u.x;
+        o.fy = u.y;
+        o.fz = v.x;
       }
     }
-    wave_sync();
-    if (lane < n_i) {
-      const double* r = red + lane * NV;
-      o.fx = r[0];
-      o.fy = r[1];
-      o.fz = r[2];
-      if constexpr (NV == 6) {
-        o.uh = 0.5 * r[3];
-        o.wh = 0.5 * r[4];
-        o.pc = (unsigned)r[5];
+    if constexpr (ENERGY || COUNT) {
+      // energy, virial and partner count (sampled steps, count mode): FP64, group order
+      double* red = L.red[w];
+      double sa[3] = {0.0, 0.0, 0.0}, sb[3] = {0.0, 0.0, 0.0};
+      for (int h = 0; h < 2; h++) {
+        const Acc<R>& X = h == 0 ? A : B;
+        wave_sync();
+        red[lane * 3 + 0] = X.u;
+        red[lane * 3 + 1] = X.w;
+        red[lane * 3 + 2] = (double)X.pc;
+        wave_sync();
+        if (lane < P) {
+          double* sv = h == 0 ? sa : sb;
+          for (int q = 0; q < G; q++) {
+            const double* r = red + (lane + q * P) * 3;
+#pragma unroll
+            for (int v = 0; v < 3; v++) sv[v] += r[v];
+          }
+        }
+      }
+      wave_sync();
+      if (lane < P) {
+#pragma unroll
+        for (int v = 0; v < 3; v++) red[lane * 3 + v] = sa[v];
+        if (lane + P < n_i) {
+#pragma unroll
+          for (int v = 0; v < 3; v++) red[(lane + P) * 3 + v] = sb[v];
+        }
+      }
+      wave_sync();
+      if (lane < n_i) {
+        const double* r = red + lane * 3;
+        o.uh = 0.5 * r[0];
+        o.wh = 0.5 * r[1];
+        o.pc = (unsigned)r[2];
       }
     }
   }
