@@ -1089,6 +1089,7 @@ struct ServedRun {
   bool polled = false;
   md_result res{};
   std::vector<double> out_pos, out_vel;
+  std::vector<double> sample_t, sample_e;  // energy samples: step, (U + K) / n
 };
 
 double drift_slope(const std::vector<double>& ts, const std::vector<double>& es) {
@@ -1149,20 +1150,25 @@ static void finish_served(md_server* sv, const std::shared_ptr<ServedRun>& r, in
 }
 
 // Bring an admitted run onto the device: geometry, binning, energy at t = 0.
+constexpr int64_t SERVED_CHUNK_CELLS = 32;
+
 static int admit_served(md_server* sv, ServedRun& r) {
   if (sv->flags & MD_SERVER_FAKE_EXECUTOR) return MD_OK;
   md_sim* s = nullptr;
   int rc = md_init(r.d.box, r.d.slices, r.d.rc, r.d.dt, r.d.precision, &s);
   if (rc) return rc;
   r.sim = s;
+  // served runs are small: short work items keep each step's critical path short
+  if ((rc = md_set_option(s, MD_OPT_CHUNK_CELLS, SERVED_CHUNK_CELLS))) return rc;
   if ((rc = md_set_stream(s, sv->stream))) return rc;
   if ((rc = md_load(s, r.d.n, r.pos.data(), r.vel.data()))) return rc;
-  if (r.d.energy_every > 0 && (rc = md_set_option(s, MD_OPT_ENERGY_EVERY, r.d.energy_every))) return rc;
   double U, K, W;
   if ((rc = md_energy_virial(s, &U, &K, &W))) return rc;
   r.res.U0 = U;
   r.res.K0 = K;
   r.res.W0 = W;
+  r.sample_t.push_back(0.0);
+  r.sample_e.push_back((U + K) / (double)std::max<int64_t>(r.d.n, 1));
   std::vector<double>().swap(r.pos);
   std::vector<double>().swap(r.vel);
   return MD_OK;
@@ -1180,16 +1186,8 @@ static int complete_served(md_server* sv, ServedRun& r) {
   r.res.U1 = U;
   r.res.K1 = K;
   r.res.W1 = W;
-  std::vector<double> ts, es;
+  std::vector<double> ts = r.sample_t, es = r.sample_e;
   const double n = (double)std::max<int64_t>(r.d.n, 1);
-  if (s->elog.empty()) {
-    ts.push_back(0.0);
-    es.push_back((r.res.U0 + r.res.K0) / n);
-  }
-  for (size_t i = 0; i + 3 < s->elog.size(); i += 4) {
-    ts.push_back(s->elog[i]);
-    es.push_back((s->elog[i + 1] + s->elog[i + 2]) / n);
-  }
   ts.push_back((double)r.d.steps);
   es.push_back((U + K) / n);
   r.res.drift_per_atom_step = drift_slope(ts, es);
@@ -1247,9 +1245,13 @@ static void server_loop(md_server* sv) {
         const int64_t left = r->d.steps - t;
         if (left <= 0) continue;
         const int64_t q = sv->quantum > 0 ? sv->quantum : 64;
+        int64_t k = std::min(left, q);
+        // launches end at the run's energy-sampling steps, which are then taken by a
+        // read-back pass: every launch runs the plain kernel variant
+        if (r->d.energy_every > 0) k = std::min(k, r->d.energy_every - t % r->d.energy_every);
         grp.push_back(r);
         sims.push_back(r->sim);
-        ks.push_back(std::min(left, q));
+        ks.push_back(k);
       }
       if (grp.empty()) continue;
       std::vector<int> st(grp.size(), MD_OK);
@@ -1275,7 +1277,18 @@ static void server_loop(md_server* sv) {
           continue;
         }
         const int64_t t = fake ? grp[i]->res.steps_done : grp[i]->sim->t;
-        if (t >= grp[i]->d.steps) finish_served(sv, grp[i], complete_served(sv, *grp[i]));
+        if (t >= grp[i]->d.steps) {
+          finish_served(sv, grp[i], complete_served(sv, *grp[i]));
+        } else if (!fake && grp[i]->d.energy_every > 0 && t % grp[i]->d.energy_every == 0) {
+          double U, K, W;
+          const int e = md_energy_virial(grp[i]->sim, &U, &K, &W);
+          if (e) {
+            finish_served(sv, grp[i], e);
+            continue;
+          }
+          grp[i]->sample_t.push_back((double)t);
+          grp[i]->sample_e.push_back((U + K) / (double)std::max<int64_t>(grp[i]->d.n, 1));
+        }
       }
     }
   }
