@@ -26,9 +26,6 @@
 
 namespace mdk {
 
-constexpr int TILE = 256;                 // candidates staged in LDS per pass
-constexpr int MAXCAND = 27 * CELL_CAP;    // candidates of one cell at most
-
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
@@ -112,11 +109,12 @@ __device__ __forceinline__ double recip64(double x) {
 // cells, staged once in LDS in layer-major order (z layer, then dx, then dy), so the
 // 27 neighbours of the cell of wave w are the contiguous entries of layers w .. w+2.
 // ---------------------------------------------------------------------------
-constexpr int BZ = WAVES;               // cells per block, one per wave
+constexpr int BZ = BLOCK_CELLS;         // cells per block, one per wave
 constexpr int BLAYERS = BZ + 2;         // staged z layers
 constexpr int BCELLS = 9 * BLAYERS;     // staged cells
 constexpr int CAPB = 27 * CELL_CAP;     // staged atoms at most (one full neighbourhood)
 constexpr int QPAD = 16;                // far sentinels after the staged atoms (FP32)
+constexpr float FAR_Q = 1e15f;          // sentinel coordinate: far from everything, |q|^2 finite
 
 struct BlockHdr {
   int nb_cell[BCELLS];     // global cell of staged cell m
@@ -128,14 +126,14 @@ struct BlockHdr {
 };
 
 template <int PREC> struct BlockLDS;
-template <> struct BlockLDS<1> {  // FP32: positions relative to the block origin + tag
+template <> struct BlockLDS<1> {  // FP32: positions relative to the block origin, |q|^2
   BlockHdr h;
   union {
     float4 q[CAPB + QPAD];
     double red[WAVES][64 * 6];
   };
 };
-template <> struct BlockLDS<0> {  // FP64: raw positions + tag
+template <> struct BlockLDS<0> {  // FP64: raw positions
   BlockHdr h;
   union {
     struct {
@@ -143,7 +141,6 @@ template <> struct BlockLDS<0> {  // FP64: raw positions + tag
     } t;
     double red[WAVES][64 * 6];
   };
-  uint16_t tag[CAPB];
 };
 
 struct ForceOut {
@@ -307,31 +304,34 @@ __device__ __forceinline__ void stage_issue(const DGeom& g, const uint32_t* ncnt
 // wrap: some staged cell of the block is a periodic image (its coordinates are shifted
 // by a box length); without it the shift is 0 and x + 0 = x exactly.
 template <int PREC>
-__device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, BlockLDS<PREC>& L, int m, int k,
+__device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, BlockLDS<PREC>& L, int m,
                                           int p, double x, double y, double z, bool wrap) {
   if constexpr (PREC == 1) {
     // FP32 origin: the column corner at the start of z0's aligned group of BZ cells, so
     // a pair's FP32 arithmetic depends on the cell only, not on how cells form blocks
     const double ox = __dmul_rn((double)R.gx, g.l[0]), oy = __dmul_rn((double)R.gy, g.l[1]),
                  oz = __dmul_rn((double)(R.z0 - R.z0 % BZ), g.l[2]);
+    float qx, qy, qz;
     if (!wrap) {
-      L.q[p] = make_float4((float)__dsub_rn(x, ox), (float)__dsub_rn(y, oy), (float)__dsub_rn(z, oz),
-                           __uint_as_float(((unsigned)m << 6) | (unsigned)k));
-      return;
+      qx = (float)__dsub_rn(x, ox);
+      qy = (float)__dsub_rn(y, oy);
+      qz = (float)__dsub_rn(z, oz);
+    } else {
+      int nx, ny, nz;
+      staged_cell_xyz(R.gx, R.gy, R.z0, m, nx, ny, nz);
+      const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
+      const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
+      const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
+      qx = (float)__dsub_rn(__dadd_rn(x, shx), ox);
+      qy = (float)__dsub_rn(__dadd_rn(y, shy), oy);
+      qz = (float)__dsub_rn(__dadd_rn(z, shz), oz);
     }
-    int nx, ny, nz;
-    staged_cell_xyz(R.gx, R.gy, R.z0, m, nx, ny, nz);
-    const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
-    const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
-    const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
-    L.q[p] = make_float4((float)__dsub_rn(__dadd_rn(x, shx), ox), (float)__dsub_rn(__dadd_rn(y, shy), oy),
-                         (float)__dsub_rn(__dadd_rn(z, shz), oz),
-                         __uint_as_float(((unsigned)m << 6) | (unsigned)k));
+    // w: |q|^2, the norm term of the matrix-core distance test
+    L.q[p] = make_float4(qx, qy, qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
   } else {
     L.t.x[p] = x;
     L.t.y[p] = y;
     L.t.z[p] = z;
-    L.tag[p] = (uint16_t)((m << 6) | k);
   }
 }
 
@@ -371,14 +371,14 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
     // far sentinels after the last staged atom: a pair-loop read past the end of the
     // list finds no partner in range
     if constexpr (PREC == 1) {
-      if (lane < QPAD) L.q[stot + lane] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+      if (lane < QPAD) L.q[stot + lane] = make_float4(FAR_Q, FAR_Q, FAR_Q, 3.0f * FAR_Q * FAR_Q);
     }
   }
   const bool wrap = R.gx == 0 || R.gx == g.G[0] - 1 || R.gy == 0 || R.gy == g.G[1] - 1 || R.z0 == 0 ||
                     R.z0 + nb >= g.G[2];
   const int tid = opaque_tid();
   for (int base = 0; base < stot; base += WG * SROUNDS) {
-    int mm[SROUNDS], kk[SROUNDS];
+    int mm[SROUNDS];
     double x[SROUNDS], y[SROUNDS], z[SROUNDS];
 #pragma unroll
     for (int r = 0; r < SROUNDS; r++) {
@@ -391,7 +391,6 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
       const int k = f - __shfl(pre, m & 63);
       const int cm = __shfl(R.nc, m & 63);
       mm[r] = m;
-      kk[r] = k;
       if (f < stot) {
         const double* jb = cblk(cells, cm);
         x[r] = jb[k];
@@ -402,7 +401,7 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
 #pragma unroll
     for (int r = 0; r < SROUNDS; r++) {
       const int f = base + tid + WG * r;
-      if (f < stot) stage_put<PREC>(g, R, L, mm[r], kk[r], f, x[r], y[r], z[r], wrap);
+      if (f < stot) stage_put<PREC>(g, R, L, mm[r], f, x[r], y[r], z[r], wrap);
     }
   }
   __syncthreads();
@@ -419,215 +418,236 @@ __device__ int stage_block(const DGeom& g, const unsigned char* cells, const uin
   return stage_commit<PREC>(g, cells, R, L);
 }
 
-// Pair forces of every atom of the cell of this wave in the staged block
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// FP32 pair forces of every atom of the cell of wave w in the staged block (Algorithm 1,
+// first loop; kernel md_v3a).  The lanes form 16 atom columns by 4 quarters: in batch u,
+// lane l holds own atom a = 16 u + (l & 15) and, of every tile of 16 consecutive
+// candidates of the cell's 27-cell window, the 4 candidates 4 (l >> 4) .. 4 (l >> 4) + 3.
+//   Pass 1 (matrix cores): per tile, one 16x16x4 FP32 MFMA with candidate rows
+//     (x, y, z, |q|^2), atom columns (-2x, -2y, -2z, 1) and accumulator |q_a|^2 - pre
+//     gives r2 - pre for all 256 pairs; its error is far below the margin of pre over
+//     the guard band, so the sign bits mark a superset of the pairs in range.
+//   Pass 2 (vector ALU): the marked pairs in slot order, with the exact FP32 arithmetic
+//     and range decision of a pair-by-pair loop; guard-band pairs are decided in FP64.
+// An atom's four quarter partials are added in quarter order, so every sum has a fixed
+// order.  Wave-level (no barrier).
+template <bool ENERGY, bool COUNT>
+__device__ void block_force32(const DGeom& g, const unsigned char* cells, const BlockLDS<1>& L, int w,
+                              ForceOut& o) {
+  const int lane = __lane_id();
+  const int col = lane & 15, quarter = lane >> 4;
+  const int n_i = o.n;
+  const int ci = 9 * (w + 1) + 4;
+  const int beg = L.h.pre[9 * w];
+  const int fe = beg + o.total;
+  const int si = L.h.pre[ci];  // own atoms in the staged list
+  // tiles of the window; the last one may reach up to 15 entries past its end, into the
+  // next z layer (two cells above the own cell: out of range) or the far sentinels
+  const int ntile = __builtin_amdgcn_readfirstlane((o.total + 15) >> 4);
+  const unsigned lo_bits = __float_as_uint(g.rc2_lo_f), hi_bits = __float_as_uint(g.rc2_hi_f);
+  const float* Lf = reinterpret_cast<const float*>(L.q);
+  for (int u = 0; 16 * u < n_i; u++) {
+    const int a = 16 * u + col;
+    const bool real = a < n_i;
+    const float4 qa = real ? L.q[si + a] : make_float4(FAR_Q, FAR_Q, FAR_Q, 0.0f);
+    const float comp = quarter == 0 ? qa.x : (quarter == 1 ? qa.y : qa.z);
+    // a missing atom's column is zero and its accumulator huge: never marked
+    const float bop = real ? (quarter == 3 ? 1.0f : -2.0f * comp) : 0.0f;
+    const float cacc = real ? qa.w - g.rc2_pre_f : 1e30f;
+    const mfma_f4 cop = {cacc, cacc, cacc, cacc};
+    Acc<float> A;
+    acc_init(A);
+    bool flag = false;
+    const float* ap = Lf + 4 * (beg + col) + quarter;  // component `quarter` of candidate `col`
+    // one matrix op in flight per wave: the operand of each op is tied to the mask the
+    // previous op completed, so the op issues only after that result has been read (and
+    // no register it reads is rewritten while it runs)
+    auto mark = [&](unsigned m, float av) {
+      asm volatile("" : "+v"(av) : "v"(m));
+      const mfma_f4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bop, cop, 0, 0, 0);
+      m = __builtin_amdgcn_alignbit(m, __float_as_uint(d[0]), 31);
+      m = __builtin_amdgcn_alignbit(m, __float_as_uint(d[1]), 31);
+      m = __builtin_amdgcn_alignbit(m, __float_as_uint(d[2]), 31);
+      return __builtin_amdgcn_alignbit(m, __float_as_uint(d[3]), 31);
+    };
+    for (int tb = 0; tb < ntile; tb += 8) {
+      const int cn = min(8, ntile - tb);
+      unsigned m = 0u;
+      if (cn == 8) {
+        // a full batch: all operand reads first, then the matrix ops
+        float av[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) av[t] = ap[64 * (tb + t)];
+#pragma unroll
+        for (int t = 0; t < 8; t++) m = mark(m, av[t]);
+      } else {
+        for (int t = 0; t < cn; t++) m = mark(m, ap[64 * (tb + t)]);
+        m <<= 32 - 4 * cn;
+      }
+      // after the reversal, bit b = 4 t + r marks candidate r of tile t
+      m = __builtin_bitreverse32(m);
+      const int fb = beg + 16 * tb + 4 * quarter;
+      // the marked pairs two at a time, in a fixed order (lowest bit first); a missing
+      // second pair is the self pair (r2 = 0: excluded exactly like every self pair)
+      while (m) {
+        const int b1 = __ffs(m) - 1;
+        m &= m - 1u;
+        const bool two = m != 0u;
+        const int b2 = __ffs(m) - 1;
+        m &= m - 1u;
+        const float4 q1 = L.q[fb + 16 * (b1 >> 2) + (b1 & 3)];
+        const float4 q2 = L.q[two ? fb + 16 * (b2 >> 2) + (b2 & 3) : si + a];
+        flag |= pair32_in<ENERGY, COUNT>(qa, q1, lo_bits, hi_bits, g.uc_f, A);
+        flag |= pair32_in<ENERGY, COUNT>(qa, q2, lo_bits, hi_bits, g.uc_f, A);
+      }
+    }
+    // guard band: decide those pairs in FP64 exactly as the FP64 path would
+    if (__ballot(flag) && flag) {
+      const double* iblk = cblk(cells, o.c);
+      const double xi = iblk[a], yi = iblk[CELL_CAP + a], zi = iblk[2 * CELL_CAP + a];
+      for (int t = 0; t < ntile; t++) {
+        for (int r = 0; r < 4; r++) {
+          const int f = beg + 16 * t + 4 * quarter + r;
+          if (f >= fe) continue;
+          const float4 q = L.q[f];
+          const float dx = qa.x - q.x, dy = qa.y - q.y, dz = qa.z - q.z;
+          const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+          const unsigned rb = __float_as_uint(r2) - 1u;
+          if (rb >= lo_bits && rb < hi_bits) {
+            // staged cell of entry f: the last one whose first entry is at or before f
+            int sm = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1)
+              if (sm + step < BCELLS && L.h.pre[sm + step] <= f) sm += step;
+            const double* jb = cblk(cells, L.h.nb_cell[sm]);
+            const int k = f - L.h.pre[sm];
+            const double ex = min_img(__dsub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
+            const double ey = min_img(__dsub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
+            const double ez = min_img(__dsub_rn(zi, jb[2 * CELL_CAP + k]), g.L[2], g.halfL[2]);
+            if (r2_exact(ex, ey, ez) <= g.rc2) pair32_add<ENERGY, COUNT>(dx, dy, dz, r2, g.uc_f, A);
+          }
+        }
+      }
+    }
+    // quarter partials of column col, added in quarter order; lane 16 u + col keeps them
+    const float sx = ((__shfl(A.fx, col) + __shfl(A.fx, col + 16)) + __shfl(A.fx, col + 32)) + __shfl(A.fx, col + 48);
+    const float sy = ((__shfl(A.fy, col) + __shfl(A.fy, col + 16)) + __shfl(A.fy, col + 32)) + __shfl(A.fy, col + 48);
+    const float sz = ((__shfl(A.fz, col) + __shfl(A.fz, col + 16)) + __shfl(A.fz, col + 32)) + __shfl(A.fz, col + 48);
+    const bool keep = quarter == u && real;
+    if (keep) {
+      o.fx = sx;
+      o.fy = sy;
+      o.fz = sz;
+    }
+    if constexpr (ENERGY || COUNT) {
+      // energy, virial and partner count (sampled steps, count mode): FP64, quarter order
+      const double su = ((__shfl(A.u, col) + __shfl(A.u, col + 16)) + __shfl(A.u, col + 32)) + __shfl(A.u, col + 48);
+      const double sw = ((__shfl(A.w, col) + __shfl(A.w, col + 16)) + __shfl(A.w, col + 32)) + __shfl(A.w, col + 48);
+      const unsigned sp = __shfl(A.pc, col) + __shfl(A.pc, col + 16) + __shfl(A.pc, col + 32) + __shfl(A.pc, col + 48);
+      if (keep) {
+        o.uh = 0.5 * su;
+        o.wh = 0.5 * sw;
+        o.pc = sp;
+      }
+    }
+  }
+}
+
+// FP64 pair forces of every atom of the cell of this wave in the staged block
 // (Algorithm 1, first loop; kernel md_v3a).  Each lane holds two atoms of the cell
 // (a and a + P, P = ceil(n/2)) and one of G candidate groups; lane (a, grp) visits
 // candidates grp, grp + G, ... of the cell's 27-cell window, so one LDS read serves two
 // pairs.  Group partials are added in group order: every atom's sum has a fixed order.
-// Whole workgroup (contains barriers); waves without a cell only take part in those.
-template <int PREC, bool ENERGY, bool COUNT>
-__device__ void block_force(const DGeom& g, const unsigned char* cells, int gx, int gy, int z0,
-                            BlockLDS<PREC>& L, ForceOut& o) {
-  using R = typename std::conditional<PREC == 1, float, double>::type;
+// Whole workgroup (contains a barrier); waves without a cell only take part in it.
+template <bool ENERGY, bool COUNT>
+__device__ void block_force64(const DGeom& g, BlockLDS<0>& L, int w, ForceOut& o) {
   const int lane = __lane_id();
-  const int w = threadIdx.x >> 6;
-  const int nb = L.h.nb;
-  const bool mine = w < nb;
-  const int ci = 9 * (w + 1) + 4;  // staged index of the wave's own cell
-  const int n_i = mine ? L.h.cnt[ci] : 0;
-  const int beg = mine ? L.h.pre[9 * w] : 0;
-  const int total = mine ? L.h.pre[9 * (w + 3)] - beg : 0;
-  o.n = n_i;
-  o.total = total;
-  o.c = mine ? L.h.nb_cell[ci] : -1;
-  o.fx = o.fy = o.fz = 0.0;
-  o.uh = o.wh = 0.0;
-  o.pc = 0;
-
-  Acc<R> A, B;
+  const int n_i = o.n;
+  const int total = o.total;
+  const int ci = 9 * (w + 1) + 4;
+  const int beg = L.h.pre[9 * w];
+  Acc<double> A, B;
   acc_init(A);
   acc_init(B);
-  int P = 1, G = 1, ia = 0, ib_ = 0;
+  int P = 1, G = 1;
   if (n_i > 0) {
     P = (n_i + 1) >> 1;
     G = 64 / P;
     if (G > 16) G = 16;
-    ia = lane % P;
+    const int ia = lane % P;
     const int grp = lane / P;
-    ib_ = ia + P;
+    const int ib_ = ia + P;
     const bool has_b = ib_ < n_i;
     const int f0 = grp < G ? beg + grp : beg + total;
     const int fe = beg + total;
     const int si = L.h.pre[ci];  // own atoms in the staged list
-    const unsigned lo_bits = __float_as_uint(g.rc2_lo_f), hi_bits = __float_as_uint(g.rc2_hi_f);
-    if constexpr (PREC == 1) {
-      // a missing atom (second atom of the lane, or a lane without a group) sits far
-      // away and never interacts
-      const float4 far = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
-      const float4 qa = grp < G ? L.q[si + ia] : far;
-      const float4 qb = grp < G && has_b ? L.q[si + ib_] : far;
-      unsigned long long band_a = 0ull, band_b = 0ull;
-      bool flag_a = false, flag_b = false;
-      // Two passes over batches of up to 32 candidate slots of this lane (slots f0 + c G).
-      // Pass 1 keeps a bit per pair, set when r2 < rc2_pre (a superset of the pairs in
-      // range); pass 2 evaluates exactly those pairs, in slot order, with the same FP32
-      // arithmetic and range decision a pair-by-pair loop would use.  Every lane runs
-      // the same pass-1 trip count: a read past the end of the window lands in the next
-      // z layer (two layers above the own cell, out of range) or in the far sentinels.
-      const int nmax = __builtin_amdgcn_readfirstlane((total + G - 1) / G);
-      const int stride = __builtin_amdgcn_readfirstlane(G);
-      for (int cb = 0; cb < nmax; cb += 32) {
-        const int cn = min(32, nmax - cb);
-        const int fb = (grp < G ? f0 : beg) + cb * stride;
-        unsigned ma = 0u, mb = 0u;
-#pragma unroll 4
-        for (int c = 0; c < cn; c++) {
-          const float4 q = L.q[fb + c * stride];
-          ma = prefilter32(qa, q, g.rc2_pre_f, ma);
-          mb = prefilter32(qb, q, g.rc2_pre_f, mb);
-        }
-        ma <<= 32 - cn;
-        mb <<= 32 - cn;
-        while (ma) {
-          const int m = __clz(ma);
-          ma ^= 0x80000000u >> m;
-          flag_a |= pair32_in<ENERGY, COUNT>(qa, L.q[fb + __mul24(m, stride)], lo_bits, hi_bits, g.uc_f, A);
-        }
-        while (mb) {
-          const int m = __clz(mb);
-          mb ^= 0x80000000u >> m;
-          flag_b |= pair32_in<ENERGY, COUNT>(qb, L.q[fb + __mul24(m, stride)], lo_bits, hi_bits, g.uc_f, B);
-        }
-      }
-      band_a = __ballot(flag_a);
-      band_b = __ballot(flag_b);
-      // guard band: decide those pairs in FP64 exactly as the FP64 path would
-      if (band_a | band_b) {
-        const double* iblk = cblk(cells, o.c);
-        for (int h = 0; h < 2; h++) {
-          Acc<float>& X = h == 0 ? A : B;
-          if (!(((h == 0 ? band_a : band_b) >> lane) & 1ull)) continue;
-          const int a = h == 0 ? ia : ib_;
-          const float4 qi = h == 0 ? qa : qb;
-          const double xi = iblk[a], yi = iblk[CELL_CAP + a], zi = iblk[2 * CELL_CAP + a];
-          for (int f = f0; f < fe; f += G) {
-            const float4 q = L.q[f];
-            const float dx = qi.x - q.x, dy = qi.y - q.y, dz = qi.z - q.z;
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const unsigned rb = __float_as_uint(r2) - 1u;
-            if (rb >= lo_bits && rb < hi_bits) {
-              const unsigned tg = __float_as_uint(q.w);
-              const double* jb = cblk(cells, L.h.nb_cell[tg >> 6]);
-              const int k = (int)(tg & 63u);
-              const double ex = min_img(__dsub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
-              const double ey = min_img(__dsub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
-              const double ez = min_img(__dsub_rn(zi, jb[2 * CELL_CAP + k]), g.L[2], g.halfL[2]);
-              if (r2_exact(ex, ey, ez) <= g.rc2) pair32_add<ENERGY, COUNT>(dx, dy, dz, r2, g.uc_f, X);
-            }
-          }
-        }
+    const double ax = L.t.x[si + ia], ay = L.t.y[si + ia], az = L.t.z[si + ia];
+    const double bx = has_b ? L.t.x[si + ib_] : 1e300, by = has_b ? L.t.y[si + ib_] : 1e300,
+                 bz = has_b ? L.t.z[si + ib_] : 1e300;
+    const bool wrap = L.h.wrap_col || L.h.wrap_layer[w] || L.h.wrap_layer[w + 2];
+    if (!wrap) {
+      // no periodic neighbour: the raw difference is the minimum image of every pair
+      // that can be in range
+#pragma unroll 2
+      for (int f = f0; f < fe; f += G) {
+        const double xj = L.t.x[f], yj = L.t.y[f], zj = L.t.z[f];
+        pair64<ENERGY, COUNT, false>(g, ax, ay, az, xj, yj, zj, A);
+        pair64<ENERGY, COUNT, false>(g, bx, by, bz, xj, yj, zj, B);
       }
     } else {
-      const double ax = L.t.x[si + ia], ay = L.t.y[si + ia], az = L.t.z[si + ia];
-      const double bx = has_b ? L.t.x[si + ib_] : 1e300, by = has_b ? L.t.y[si + ib_] : 1e300,
-                   bz = has_b ? L.t.z[si + ib_] : 1e300;
-      const bool wrap = L.h.wrap_col || L.h.wrap_layer[w] || L.h.wrap_layer[w + 2];
-      if (!wrap) {
-        // no periodic neighbour: the raw difference is the minimum image of every pair
-        // that can be in range
-#pragma unroll 2
-        for (int f = f0; f < fe; f += G) {
-          const double xj = L.t.x[f], yj = L.t.y[f], zj = L.t.z[f];
-          pair64<ENERGY, COUNT, false>(g, ax, ay, az, xj, yj, zj, A);
-          pair64<ENERGY, COUNT, false>(g, bx, by, bz, xj, yj, zj, B);
-        }
-      } else {
-        for (int f = f0; f < fe; f += G) {
-          const double xj = L.t.x[f], yj = L.t.y[f], zj = L.t.z[f];
-          pair64<ENERGY, COUNT, true>(g, ax, ay, az, xj, yj, zj, A);
-          pair64<ENERGY, COUNT, true>(g, bx, by, bz, xj, yj, zj, B);
-        }
+      for (int f = f0; f < fe; f += G) {
+        const double xj = L.t.x[f], yj = L.t.y[f], zj = L.t.z[f];
+        pair64<ENERGY, COUNT, true>(g, ax, ay, az, xj, yj, zj, A);
+        pair64<ENERGY, COUNT, true>(g, bx, by, bz, xj, yj, zj, B);
       }
     }
   }
   // every wave is done with the staged positions; the same LDS now holds the partials
   __syncthreads();
   if (n_i > 0) {
-    // Forces: both atoms' group partials per lane, summed in group order (a fixed order,
-    // the same in every kernel variant), then handed to the lane of each atom.
-    if constexpr (PREC == 1) {
-      // FP32: two float4 per lane, FP32 sums
-      float4* r4 = reinterpret_cast<float4*>(L.red[w]);
-      r4[2 * lane] = make_float4((float)A.fx, (float)A.fy, (float)A.fz, (float)B.fx);
-      r4[2 * lane + 1] = make_float4((float)B.fy, (float)B.fz, 0.0f, 0.0f);
-      wave_sync();
-      float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, s4 = 0.0f, s5 = 0.0f;
-      if (lane < P) {
-        for (int q = 0; q < G; q++) {
-          const float4 u = r4[2 * (lane + q * P)], v = r4[2 * (lane + q * P) + 1];
-          s0 += u.x;
-          s1 += u.y;
-          s2 += u.z;
-          s3 += u.w;
-          s4 += v.x;
-          s5 += v.y;
-        }
-      }
-      wave_sync();
-      if (lane < P) {
-        r4[lane] = make_float4(s0, s1, s2, 0.0f);
-        if (lane + P < n_i) r4[lane + P] = make_float4(s3, s4, s5, 0.0f);
-      }
-      wave_sync();
-      if (lane < n_i) {
-        const float4 t = r4[lane];
-        o.fx = t.x;
-        o.fy = t.y;
-        o.fz = t.z;
-      }
-    } else {
-      // FP64: three double2 per lane
-      double2* r2 = reinterpret_cast<double2*>(L.red[w]);
-      r2[3 * lane] = make_double2((double)A.fx, (double)A.fy);
-      r2[3 * lane + 1] = make_double2((double)A.fz, (double)B.fx);
-      r2[3 * lane + 2] = make_double2((double)B.fy, (double)B.fz);
-      wave_sync();
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0;
-      if (lane < P) {
-        for (int q = 0; q < G; q++) {
-          const int j = 3 * (lane + q * P);
-          const double2 u = r2[j], v = r2[j + 1], t = r2[j + 2];
-          s0 += u.x;
-          s1 += u.y;
-          s2 += v.x;
-          s3 += v.y;
-          s4 += t.x;
-          s5 += t.y;
-        }
-      }
-      wave_sync();
-      if (lane < P) {
-        r2[2 * lane] = make_double2(s0, s1);
-        r2[2 * lane + 1] = make_double2(s2, 0.0);
-        if (lane + P < n_i) {
-          r2[2 * (lane + P)] = make_double2(s3, s4);
-          r2[2 * (lane + P) + 1] = make_double2(s5, 0.0);
-        }
-      }
-      wave_sync();
-      if (lane < n_i) {
-        const double2 u = r2[2 * lane], v = r2[2 * lane + 1];
-        o.fx = u.x;
-        o.fy = u.y;
-        o.fz = v.x;
+    // Forces: both atoms' group partials per lane (three double2), summed in group order,
+    // then handed to the lane of each atom.
+    double2* r2 = reinterpret_cast<double2*>(L.red[w]);
+    r2[3 * lane] = make_double2(A.fx, A.fy);
+    r2[3 * lane + 1] = make_double2(A.fz, B.fx);
+    r2[3 * lane + 2] = make_double2(B.fy, B.fz);
+    wave_sync();
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0;
+    if (lane < P) {
+      for (int q = 0; q < G; q++) {
+        const int j = 3 * (lane + q * P);
+        const double2 u = r2[j], v = r2[j + 1], t = r2[j + 2];
+        s0 += u.x;
+        s1 += u.y;
+        s2 += v.x;
+        s3 += v.y;
+        s4 += t.x;
+        s5 += t.y;
       }
     }
+    wave_sync();
+    if (lane < P) {
+      r2[2 * lane] = make_double2(s0, s1);
+      r2[2 * lane + 1] = make_double2(s2, 0.0);
+      if (lane + P < n_i) {
+        r2[2 * (lane + P)] = make_double2(s3, s4);
+        r2[2 * (lane + P) + 1] = make_double2(s5, 0.0);
+      }
+    }
+    wave_sync();
+    if (lane < n_i) {
+      const double2 u = r2[2 * lane], v = r2[2 * lane + 1];
+      o.fx = u.x;
+      o.fy = u.y;
+      o.fz = v.x;
+    }
     if constexpr (ENERGY || COUNT) {
-      // energy, virial and partner count (sampled steps, count mode): FP64, group order
+      // energy, virial and partner count (sampled steps, count mode): group order
       double* red = L.red[w];
       double sa[3] = {0.0, 0.0, 0.0}, sb[3] = {0.0, 0.0, 0.0};
       for (int h = 0; h < 2; h++) {
-        const Acc<R>& X = h == 0 ? A : B;
+        const Acc<double>& X = h == 0 ? A : B;
         wave_sync();
         red[lane * 3 + 0] = X.u;
         red[lane * 3 + 1] = X.w;
@@ -660,6 +680,25 @@ __device__ void block_force(const DGeom& g, const unsigned char* cells, int gx, 
       }
     }
   }
+}
+
+// Pair forces of every atom of the cell of this wave in the staged block: header of
+// the wave's cell, then the FP32 or FP64 pair loop.  Whole workgroup.
+template <int PREC, bool ENERGY, bool COUNT>
+__device__ void block_force(const DGeom& g, const unsigned char* cells, BlockLDS<PREC>& L, ForceOut& o) {
+  const int w = threadIdx.x >> 6;
+  const bool mine = w < L.h.nb;
+  const int ci = 9 * (w + 1) + 4;  // staged index of the wave's own cell
+  o.n = mine ? L.h.cnt[ci] : 0;
+  o.total = mine ? L.h.pre[9 * (w + 3)] - L.h.pre[9 * w] : 0;
+  o.c = mine ? L.h.nb_cell[ci] : -1;
+  o.fx = o.fy = o.fz = 0.0;
+  o.uh = o.wh = 0.0;
+  o.pc = 0;
+  if constexpr (PREC == 1)
+    block_force32<ENERGY, COUNT>(g, cells, L, w, o);
+  else
+    block_force64<ENERGY, COUNT>(g, L, w, o);
 }
 
 // Walk the cells [b, e) of one slice (local indices, z fastest) block by block; fn(o)
@@ -702,7 +741,7 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
         o.id = cids(ib)[lane];
       }
     }
-    block_force<PREC, ENERGY, COUNT>(g, cells, R.gx, R.gy, R.z0, L, o);
+    block_force<PREC, ENERGY, COUNT>(g, cells, L, o);
     x += nb;
     const bool more = x < e;
     if (more) issue(x, R);
@@ -1235,7 +1274,6 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
   __shared__ Item s_it;
   __shared__ int s_ok;
   __shared__ long long s_ticket;
-  const int wave = threadIdx.x >> 6;
   const long long total = la.total;
   while (true) {
     if (threadIdx.x == 0) {

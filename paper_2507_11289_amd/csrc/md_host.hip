@@ -123,9 +123,16 @@ static int make_geom(const double box[3], int slices, double rc, double dt, int 
   if ((double)fhi < hi) fhi = std::nextafter(fhi, 1e30f);
   g->rc2_lo_f = flo;
   g->rc2_hi_f = fhi;
-  // pre-filter threshold, 2^-10 above the band: covers the rounding of any FP32
-  // evaluation order of r2 many times over
-  g->rc2_pre_f = (float)(hi * (1.0 + std::ldexp(1.0, -10)));
+  // Pre-filter threshold.  The FP32 force pass estimates r2 - pre on the matrix cores
+  // as |q_c|^2 - 2 q_a.q_c + (|q_a|^2 - pre), from staged coordinates q relative to the
+  // block origin (|x| <= 2 lx, |y| <= 2 ly, |z| <= (BLOCK_CELLS + 1) lz, so |q|^2 <= M).
+  // Whatever the order and rounding of its sums, that estimate is within
+  // 2^-24 (31 M + 7 pre) of the exact r2 - pre; the threshold lies 2^-10 rc^2 above the
+  // guard band plus 2^-18 (M + hi), more than twice that, so every pair the exact FP32
+  // arithmetic puts at or below the band is marked.
+  const double M = 1.01 * (4.0 * g->l[0] * g->l[0] + 4.0 * g->l[1] * g->l[1] +
+                           (double)((BLOCK_CELLS + 1) * (BLOCK_CELLS + 1)) * g->l[2] * g->l[2]);
+  g->rc2_pre_f = (float)(hi * (1.0 + std::ldexp(1.0, -10)) + std::ldexp(M + hi, -18));
   g->rc2_f = (float)g->rc2;
   g->uc_f = (float)g->uc;
   g->cps = (int)cps;

@@ -18,6 +18,7 @@ constexpr int CELL_DOUBLES = 6 * CELL_CAP;   // x y z vx vy vz
 constexpr int CELL_BYTES = CELL_DOUBLES * 8 + CELL_CAP * 4;  // 3328
 constexpr int WG = 256;                      // threads per workgroup (4 waves)
 constexpr int WAVES = WG / 64;
+constexpr int BLOCK_CELLS = WAVES;            // cells of one z-column per staged block (one per wave)
 
 // error word bits
 constexpr uint32_t ERR_NONFINITE = 1u;
@@ -38,7 +39,8 @@ struct DGeom {
   float rc2_f;     // rc^2 in FP32
   float rc2_lo_f;  // FP32 pairs with r2 <= rc2_lo_f are in range for certain
   float rc2_hi_f;  // FP32 pairs with r2 >  rc2_hi_f are out of range for certain
-  float rc2_pre_f; // pre-filter: every pair with FP32 r2 <= rc2_hi_f has r2 < rc2_pre_f
+  float rc2_pre_f; // pre-filter threshold: every pair with FP32 r2 <= rc2_hi_f has a matrix-core
+                   // estimate of r2 below it
   float uc_f;
   int S;           // slices
   int ncx;         // cell layers per slice
