@@ -35,14 +35,14 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_11289_amd", "csrc", "md_device.hi
 # counters on a plain device copy of known size (profiles/persistent_f32_lean_lj_fluid_4m.md).
 # Valid only for the kernel source they were taken on (sha256 below); otherwise null.
 TRAFFIC = {
-    "source_sha256": "1de159bbcccf69c5aa6ca07e7d6f38d30eef4c8ae513e5e20d94847c86aa23e5",
+    "source_sha256": "dc18884844c06a77e3b87f71a32835410f6e0cbfd7d46da3fafa849416da42fd",
     "workload": "lj_fluid_4m",
     "steps_per_launch": 100,
-    "fetch_kib_per_launch": 68550365,      # FETCH_SIZE, mean of 3 dispatches
-    "write_kib_per_launch": 26473854,      # WRITE_SIZE, mean of 3 dispatches
+    "fetch_kib_per_launch": 68408163,      # FETCH_SIZE, mean of 3 dispatches
+    "write_kib_per_launch": 26561212,      # WRITE_SIZE, mean of 3 dispatches
     "copy_fetch_factor": 0.50001,          # FETCH_SIZE KiB / KiB really read by a 1 GiB copy
     "copy_write_factor": 1.00000,          # WRITE_SIZE KiB / KiB really written by it
-    "hbm_bytes_per_launch": 1.6750e+11,
+    "hbm_bytes_per_launch": 1.6730e+11,
 }
 
 
