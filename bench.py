@@ -28,12 +28,13 @@ METRIC = "atom-steps/s at 4M-atom LJ fluid, FP32-force vs FP64 plain; served p50
 FP32_PEAK = 157.3      # TFLOP/s, MI355X vector FP32 (packed) -- the figure the roofline uses
 FP64_PEAK = 78.6       # TFLOP/s, MI355X vector FP64
 HBM_PEAK = 8000.0      # GB/s
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_11289_amd", "csrc", "md_device.hip")
+# the kernel and the host code that sizes its work items: both shape its memory traffic
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11289_amd", "csrc", f) for f in ("md_device.hip", "md_host.hip")]
 
 # HBM traffic of one 100-step launch of the FP32-force persistent kernel on lj_fluid_4m,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) and the same
 # counters on a plain device copy of known size (profiles/persistent_f32_lean_lj_fluid_4m.md).
-# Valid only for the kernel source they were taken on (sha256 below); otherwise null.
+# Valid only for the kernel and host sources they were taken on (sha256 below); otherwise null.
 TRAFFIC = {
     "source_sha256": "dc18884844c06a77e3b87f71a32835410f6e0cbfd7d46da3fafa849416da42fd",
     "workload": "lj_fluid_4m",
@@ -51,7 +52,10 @@ def log(*a):
 
 
 def source_sha():
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def timed_leg(sysm, prec, steps, warmup, stream, launch_steps):

@@ -398,9 +398,19 @@ static int device_ready() {
   return MD_OK;
 }
 
-static int auto_chunks(const DGeom& g, int64_t chunk_cells) {
-  int64_t cc = chunk_cells > 0 ? chunk_cells : 128;
-  int64_t nch = (g.cps + cc - 1) / cc;
+// Work items per slice and phase.  Without a given cell count an item holds about
+// ATOMS_PER_ITEM atoms (at least 32 cells): fewer, larger items mean fewer queue
+// operations and fewer L2 invalidations at item start, more and smaller ones balance
+// better; these sizes were the fastest on the homogeneous and slab workloads.
+static int auto_chunks(const DGeom& g, int64_t chunk_cells, int64_t n_atoms) {
+  int64_t nch;
+  if (chunk_cells > 0) {
+    nch = (g.cps + chunk_cells - 1) / chunk_cells;
+  } else {
+    const double atoms_per_item = g.prec == 1 ? 2600.0 : 1900.0;
+    nch = std::llround((double)n_atoms / ((double)g.S * atoms_per_item));
+    nch = std::min<int64_t>(nch, (g.cps + 31) / 32);
+  }
   if (nch < 1) nch = 1;
   if (nch > g.cps) nch = g.cps;
   if (nch > 4096) nch = 4096;
@@ -451,7 +461,7 @@ extern "C" int md_init(const double box[3], int slices, double rc, double dt, in
     return rc_;
   }
   s->ls = new LaunchScratch();
-  s->nch = auto_chunks(g, 0);
+  s->nch = auto_chunks(g, 0, 0);
   *out = s.release();
   return MD_OK;
 }
@@ -493,7 +503,7 @@ extern "C" int md_set_option(md_sim* s, int key, int64_t value) {
     case MD_OPT_CHUNK_CELLS:
       if (value < 0) return fail(MD_EINVAL, "chunk cells must be >= 0");
       s->chunk_cells = value;
-      s->nch = auto_chunks(s->g, value);
+      s->nch = auto_chunks(s->g, value, s->n);
       return MD_OK;
     case MD_OPT_COUNT_PAIRS:
       s->count_pairs = value != 0;
@@ -619,6 +629,7 @@ extern "C" int md_load(md_sim* s, int64_t n, const double* pos, const double* ve
     return rc;
   }
   s->n = n;
+  s->nch = auto_chunks(s->g, s->chunk_cells, n);
   s->t = 0;
   s->par = 0;
   s->first = 1;
