@@ -136,6 +136,62 @@ def test_brute_force_tiny_systems():
                 assert st.candidates == int(c["cand"].sum())
 
 
+def cutoff_pairs(seed=11):
+    """Isolated atom pairs at separations rc (1 + delta), delta from -2^-12 to +2^-12:
+    some pairs lie inside the FP32 guard band |r2 - rc^2| <= 2^-16 rc^2 (decided again in
+    FP64), some just outside it, some exactly at the FP64 cutoff decision.  Pair centres
+    are 7.5 apart, so no atom has a partner other than its own (at most 2.25 from the
+    centre)."""
+    rc = 2.5
+    rng = np.random.default_rng(seed)
+    deltas = [-2.0 ** -12, -2.0 ** -17, -2.0 ** -20, -2.0 ** -26, 0.0,
+              2.0 ** -26, 2.0 ** -20, 2.0 ** -17, 2.0 ** -12]
+    box = (45.0, 30.0, 30.0)
+    pos = []
+    n = 0
+    for i in range(6):
+        for j in range(4):
+            for k in range(4):
+                d = rc * (1.0 + deltas[n % len(deltas)])
+                u = rng.normal(size=3)
+                u /= np.linalg.norm(u)
+                if n % 4 == 0:
+                    u = np.array([1.0, 0.0, 0.0])
+                c = np.array([3.75 + 7.5 * i, 3.75 + 7.5 * j, 3.75 + 7.5 * k]) + rng.uniform(-1.0, 1.0, 3)
+                pos += [c - 0.5 * d * u, c + 0.5 * d * u]
+                n += 1
+    return box, rc, np.mod(np.array(pos), box)
+
+
+def test_cutoff_decisions_at_the_guard_band():
+    box, rc, pos = cutoff_pairs()
+    g = ref.geometry(box, 3, rc)
+    Fb, Ub, Wb, Pb = ref.forces_brute(g, pos)
+    c = ref.forces_cells(g, pos)
+    # the construction reaches both sides of the cutoff and the inside of the FP32 band
+    a, b = pos[0::2], pos[1::2]
+    dd = a - b
+    dd -= np.array(box) * np.round(dd / np.array(box))
+    r2 = (dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]
+    band = np.abs(r2 - rc * rc) <= 2.0 ** -16 * rc * rc
+    assert band.sum() >= 20 and 0 < Pb < len(r2)
+    assert ((r2 <= rc * rc) & band).any() and ((r2 > rc * rc) & band).any()
+    vel = np.zeros_like(pos)
+    for prec in PRECS:
+        say(f"[gpu] cutoff pairs: {len(r2)} pairs, {int(band.sum())} in the FP32 band, precision={prec}")
+        with md.Sim(box, 3, rc, 0.005, prec) as sim:
+            sim.set_option(md.OPT_COUNT_PAIRS, 1)
+            sim.load(pos, vel)
+            _, _, F = sim.state()
+            # an atom whose only partner is out of range feels exactly nothing
+            np.testing.assert_array_equal(F[np.all(Fb == 0.0, axis=1)], 0.0)
+            assert ref.force_error(F, Fb, c["scale"]).max() <= TOL[prec]
+            sim.step(1)
+            st = sim.stats()
+            assert st.in_range == 2 * Pb
+            assert st.candidates == int(c["cand"].sum())
+
+
 def run_state(s, prec, nsteps, order=None, seed=1, chunk=0):
     with md.Sim(s.box, s.slices, s.rc, s.dt, prec) as sim:
         if order is not None:
