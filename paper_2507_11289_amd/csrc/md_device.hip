@@ -423,7 +423,8 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 // FP32 pair forces of every atom of the cell of wave w in the staged block (Algorithm 1,
 // first loop; kernel md_v3a).  The lanes form 16 atom columns by 4 quarters: in batch u,
 // lane l holds own atom a = 16 u + (l & 15) and, of every tile of 16 consecutive
-// candidates of the cell's 27-cell window, the 4 candidates 4 (l >> 4) .. 4 (l >> 4) + 3.
+// candidates of the cell's 27-cell window, the 4 candidates (l >> 4) + 4 r, r < 4 (every
+// fourth one, so each lane samples the whole window).
 //   Pass 1 (matrix cores): per tile, one 16x16x4 FP32 MFMA with candidate rows
 //     (x, y, z, |q|^2), atom columns (-2x, -2y, -2z, 1) and accumulator |q_a|^2 - pre
 //     gives r2 - pre for all 256 pairs; its error is far below the margin of pre over
@@ -459,7 +460,9 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, const 
     Acc<float> A;
     acc_init(A);
     bool flag = false;
-    const float* ap = Lf + 4 * (beg + col) + quarter;  // component `quarter` of candidate `col`
+    // row i = 4 r + s of a tile is candidate s + 4 r of it (lane quarter s then holds
+    // every fourth candidate); the lane supplies component `quarter` of row `col`
+    const float* ap = Lf + 4 * (beg + (col >> 2) + 4 * (col & 3)) + quarter;
     // one matrix op in flight per wave: the operand of each op is tied to the mask the
     // previous op completed, so the op issues only after that result has been read (and
     // no register it reads is rewritten while it runs)
@@ -485,9 +488,10 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, const 
         for (int t = 0; t < cn; t++) m = mark(m, ap[64 * (tb + t)]);
         m <<= 32 - 4 * cn;
       }
-      // after the reversal, bit b = 4 t + r marks candidate r of tile t
+      // after the reversal, bit b = 4 t + r marks row 4 quarter + r of tile t, i.e.
+      // candidate 16 t + quarter + 4 r = 4 b + quarter of the batch
       m = __builtin_bitreverse32(m);
-      const int fb = beg + 16 * tb + 4 * quarter;
+      const int fb = beg + 16 * tb + quarter;
       // the marked pairs two at a time, in a fixed order (lowest bit first); a missing
       // second pair is the self pair (r2 = 0: excluded exactly like every self pair)
       while (m) {
@@ -496,8 +500,8 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, const 
         const bool two = m != 0u;
         const int b2 = __ffs(m) - 1;
         m &= m - 1u;
-        const float4 q1 = L.q[fb + 16 * (b1 >> 2) + (b1 & 3)];
-        const float4 q2 = L.q[two ? fb + 16 * (b2 >> 2) + (b2 & 3) : si + a];
+        const float4 q1 = L.q[fb + 4 * b1];
+        const float4 q2 = L.q[two ? fb + 4 * b2 : si + a];
         flag |= pair32_in<ENERGY, COUNT>(qa, q1, lo_bits, hi_bits, g.uc_f, A);
         flag |= pair32_in<ENERGY, COUNT>(qa, q2, lo_bits, hi_bits, g.uc_f, A);
       }
@@ -508,7 +512,7 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, const 
       const double xi = iblk[a], yi = iblk[CELL_CAP + a], zi = iblk[2 * CELL_CAP + a];
       for (int t = 0; t < ntile; t++) {
         for (int r = 0; r < 4; r++) {
-          const int f = beg + 16 * t + 4 * quarter + r;
+          const int f = beg + 16 * t + quarter + 4 * r;
           if (f >= fe) continue;
           const float4 q = L.q[f];
           const float dx = qa.x - q.x, dy = qa.y - q.y, dz = qa.z - q.z;
