@@ -105,7 +105,8 @@ typedef struct md_stats {
                                   launch stream) */
     int32_t last_launches;     /* persistent launches of the last md_step */
     int32_t persistent_grid;   /* workgroups of the last persistent launch */
-    int32_t chunks_per_slice;  /* work items per slice and phase */
+    int32_t chunks_per_slice;  /* force work items per slice and step (finalise items: a
+                                  quarter as many, rounded up, under the dataflow scheduler) */
     int32_t precision;         /* md_precision */
     int32_t poisoned;          /* 1 after a failed md_step */
 } md_stats;

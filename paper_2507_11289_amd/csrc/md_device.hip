@@ -1212,8 +1212,8 @@ __device__ void run_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& ws, 
     run_p2b_item(ra, it, &s_red[0][0], s_cnt, ra.abort);
   } else {
     const int dst = (ra.par0 + it.k + 1) & 1;
-    const int b = (int)((long long)ra.g.cps * it.chunk / ra.nch);
-    const int e = (int)((long long)ra.g.cps * (it.chunk + 1) / ra.nch);
+    const int b = (int)((long long)ra.g.cps * it.chunk / ra.nchA);
+    const int e = (int)((long long)ra.g.cps * (it.chunk + 1) / ra.nchA);
     const int cbase = it.slice * ra.g.cps;
     p1_range(ra, cbase + b, cbase + e, dst, wave, ra.abort);
   }
@@ -1243,7 +1243,7 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
   // the step's update of slice i (phase 0, or 2 with the thermostat) counts towards the
   // finalise of i-1, i, i+1; a finalise counts towards the next force items
   const bool update = it.phase != 1;
-  const unsigned need = 3u * (unsigned)ra.nch * (unsigned)(it.k + 1);
+  const unsigned need = 3u * (unsigned)(update ? ra.nch : ra.nchA) * (unsigned)(it.k + 1);
   uint32_t* cnt = update ? ra.cntF : ra.cntA;
   for (int d = -1; d <= 1; d++) {
     const int j = (it.slice + d + S) % S;
@@ -1260,9 +1260,10 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
       phase = 0;
       k = it.k + 1;
     }
+    const int nq = phase == 1 ? ra.nchA : ra.nch;
     const unsigned long long base =
-        __hip_atomic_fetch_add(la.q_tail, (unsigned long long)ra.nch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int ch = 0; ch < ra.nch; ch++)
+        __hip_atomic_fetch_add(la.q_tail, (unsigned long long)nq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int ch = 0; ch < nq; ch++)
       __hip_atomic_store(la.q + base + ch, enc_item(it.run, k, phase, j, ch), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -1319,6 +1320,7 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
           }
           const RunArgs& ra = la.runs[rlo];
           const int local = (int)(rem - la.run_prefix[rlo]);
+          // fixed claim orders: both phases have nch items per slice (nchA == nch)
           const int entry = local / ra.nch;
           const unsigned ord = ra.order[entry];
           it.run = rlo;
@@ -1338,7 +1340,7 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
     if (threadIdx.x == 0) {
       bool ok = !ld_relaxed(ra.abort);
       if (la.mode != 0 && ok) {
-        const unsigned need = (unsigned)(it.k + 1) * (unsigned)ra.nch;
+        const unsigned need = (unsigned)(it.k + 1) * (unsigned)(it.phase == 0 ? ra.nchA : ra.nch);
         ok = wait_counters(la, it.phase == 0 ? ra.cntA : ra.cntF, ra.g.S, it.slice, need, ra.err, ra.abort);
       }
       // one acquire for the workgroup: the barrier below orders every wave after it
@@ -1412,7 +1414,7 @@ __global__ void init_launch_kernel(LaunchArgs la) {
     const RunArgs& ra = la.runs[r];
     if (i == 0) *ra.abort = 0u;
     for (long long s = i; s < ra.g.S; s += stride) {
-      ra.cntA[s] = la.mode == 0 ? 0u : (uint32_t)ra.nch;
+      ra.cntA[s] = la.mode == 0 ? 0u : (uint32_t)ra.nchA;
       ra.cntF[s] = 0u;
       if (ra.cntK) ra.cntK[s] = 0u;
     }

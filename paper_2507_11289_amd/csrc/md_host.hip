@@ -398,6 +398,10 @@ static int device_ready() {
   return MD_OK;
 }
 
+// Finalise items per slice and step are the force items' count divided by this (rounded
+// up) under the dataflow scheduler.
+constexpr int64_t FINALISE_MERGE = 4;
+
 // Work items per slice and phase.  Without a given cell count an item holds about
 // ATOMS_PER_ITEM atoms (at least 32 cells): fewer, larger items mean fewer queue
 // operations and fewer L2 invalidations at item start, more and smaller ones balance
@@ -662,8 +666,8 @@ static long long watchdog_ticks(int64_t ms) {
 
 // Per-run preparation of a launch of k steps: claim table, energy/migration buffers,
 // and the device-visible RunArgs.
-static int prepare_run(md_sim* s, int64_t k_steps, hipStream_t st, RunArgs* ra, int64_t* nsample_out,
-                       int64_t* first_j_out) {
+static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st, RunArgs* ra,
+                       int64_t* nsample_out, int64_t* first_j_out) {
   const DGeom& g = s->g;
   int rc;
   if (s->order_dirty) {
@@ -714,10 +718,14 @@ static int prepare_run(md_sim* s, int64_t k_steps, hipStream_t st, RunArgs* ra, 
   ra->par0 = s->par;
   ra->first = s->first;
   ra->nch = s->nch;
+  // finalise items: a quarter as many as force items under the dataflow scheduler (each
+  // is short and every item pays a release and an acquire); as many with a fixed claim
+  // order, whose tickets enumerate equal chunk counts for both phases
+  ra->nchA = dataflow ? (int)std::max<int64_t>(1, (s->nch + FINALISE_MERGE - 1) / FINALISE_MERGE) : s->nch;
   ra->every = (int)s->every;
   ra->count = s->count_pairs ? 1 : 0;
   ra->fail_at = s->fail_at;
-  ra->ips = 2 * g.S * s->nch;
+  ra->ips = g.S * (s->nch + ra->nchA);
   if (s->thermo_T > 0.0) {
     if (s->order_kind != MD_ORDER_DATAFLOW)
       return fail(MD_EINVAL, "the thermostat runs with the dataflow scheduler only");
@@ -732,7 +740,7 @@ static int prepare_run(md_sim* s, int64_t k_steps, hipStream_t st, RunArgs* ra, 
     ra->fbuf = s->d_fbuf;
     ra->kpart = s->d_kpart;
     ra->cntK = s->b.cntK;
-    ra->ips = 3 * g.S * s->nch;
+    ra->ips = g.S * (2 * s->nch + ra->nchA);
   }
   *nsample_out = nsample;
   *first_j_out = first_j;
@@ -804,9 +812,11 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   std::vector<long long> prefix(R + 1, 0);
   int max_slices = 1;
   const int prec = sims[idx[0]]->prec;
+  const int mode = sims[idx[0]]->order_kind == MD_ORDER_DATAFLOW ? 0 : 1;
   for (size_t q = 0; q < R; q++) {
     md_sim* s = sims[idx[q]];
-    if ((rc = prepare_run(s, ksteps[idx[q]], st, &ra[q], &nsample[idx[q]], &first_j[idx[q]]))) return rc;
+    if ((rc = prepare_run(s, ksteps[idx[q]], mode == 0, st, &ra[q], &nsample[idx[q]], &first_j[idx[q]])))
+      return rc;
     prefix[q + 1] = prefix[q] + ra[q].ips;
     max_slices = std::max(max_slices, s->g.S);
   }
@@ -822,7 +832,6 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   HIPCHK(hipMemcpy(ls.d_run_prefix, prefix.data(), prefix.size() * sizeof(long long), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(ls.d_round_base, rb.data(), rb.size() * sizeof(long long), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(ls.d_round_active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice));
-  const int mode = sims[idx[0]]->order_kind == MD_ORDER_DATAFLOW ? 0 : 1;
   const size_t total = (size_t)rb[(size_t)nrounds];
   if (nrounds >= (1 << 19)) return fail(MD_EINVAL, "too many steps in one launch");
   if (mode == 0) {

@@ -55,7 +55,8 @@ struct RunArgs {
   unsigned char* cells[2];
   uint32_t* ncnt[2];
   uint32_t* nin[2];
-  uint32_t* cntA;               // per slice: finalise items completed in this launch (+nch at start)
+  uint32_t* cntA;               // per slice: finalise items completed in this launch (+nchA at start
+                                // with a fixed claim order)
   uint32_t* cntF;               // per slice: force/integrate items completed in this launch
   double* epart;                // [nsample][S][nch][3] partial U, K, W (energy steps)
   uint32_t* miglog;             // [nsteps][S][2] or null
@@ -68,11 +69,14 @@ struct RunArgs {
   int nsteps;                   // steps in this launch
   int par0;                     // parity of the sorted buffer at t0
   int first;                    // 1: stored velocities are v(t0) (not half-step velocities)
-  int nch;                      // work items per slice and phase
+  int nch;                      // force (and thermostat integrate) items per slice and step
+  int nchA;                     // finalise items per slice and step (fewer than nch with the
+                                // dataflow scheduler: they are short, and every item pays a
+                                // release and an acquire)
   int every;                    // energy sampling interval (0 = none)
   int count;                    // count candidates / in-range partners
   long long fail_at;            // debug fault injection step (-1 off)
-  int ips;                      // items per step: 2 * S * nch (3 * S * nch with the thermostat)
+  int ips;                      // items per step: S * (nch + nchA) (+ S * nch with the thermostat)
   double thermo_T;              // velocity-scaling thermostat target temperature (0: off)
   double* fbuf;                 // thermostat: F(t) per slot of the step's cells [ncell][3][64]
   double* kpart;                // thermostat: [S][nch][2] kinetic energy and atoms of v(t)
