@@ -1279,6 +1279,8 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
   __shared__ Item s_it;
   __shared__ int s_ok;
   __shared__ long long s_ticket;
+  __shared__ RunArgs s_ra;
+  static_assert(sizeof(RunArgs) % 4 == 0, "RunArgs is copied as dwords");
   const long long total = la.total;
   while (true) {
     if (threadIdx.x == 0) {
@@ -1336,12 +1338,21 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
     __syncthreads();
     const Item it = s_it;
     if (it.go == 0) break;
-    const RunArgs& ra = la.runs[it.run];
+    // The item's run arguments, copied into LDS (they do not change during a launch):
+    // read from global memory, every field would be loaded again after each store of
+    // the item (the compiler must assume they may alias), each load waiting for all of
+    // the wave's outstanding memory operations; LDS cannot alias global memory.
+    {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(la.runs + it.run);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(&s_ra);
+      for (int i = threadIdx.x; i < (int)(sizeof(RunArgs) / 4); i += WG) dst[i] = src[i];
+    }
+    const RunArgs& rg = la.runs[it.run];  // thread 0 before the barrier below: the global copy
     if (threadIdx.x == 0) {
-      bool ok = !ld_relaxed(ra.abort);
+      bool ok = !ld_relaxed(rg.abort);
       if (la.mode != 0 && ok) {
-        const unsigned need = (unsigned)(it.k + 1) * (unsigned)(it.phase == 0 ? ra.nchA : ra.nch);
-        ok = wait_counters(la, it.phase == 0 ? ra.cntA : ra.cntF, ra.g.S, it.slice, need, ra.err, ra.abort);
+        const unsigned need = (unsigned)(it.k + 1) * (unsigned)(it.phase == 0 ? rg.nchA : rg.nch);
+        ok = wait_counters(la, it.phase == 0 ? rg.cntA : rg.cntF, rg.g.S, it.slice, need, rg.err, rg.abort);
       }
       // one acquire for the workgroup: the barrier below orders every wave after it
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -1358,6 +1369,7 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
       }
     }
     __syncthreads();
+    const RunArgs& ra = s_ra;  // after the barrier: the LDS copy
     const int ok = s_ok;
     if (ok) run_item<PREC, FULL, NVT>(ra, it, ws, s_red, s_cnt);
     // every wave's stores have reached the L2 before the barrier (the barrier itself
