@@ -120,6 +120,7 @@ struct BlockHdr {
   int nb_cell[BCELLS];     // global cell of staged cell m
   int cnt[BCELLS];         // atoms of staged cell m
   int pre[BCELLS + 1];     // first staged entry of cell m
+  double org[3];           // origin of the block's FP32 coordinates
   int nb;                  // cells of this block (after the capacity check)
   int wrap_col;            // the column touches a periodic boundary in x or y
   int wrap_layer[BLAYERS]; // z layer is a periodic image
@@ -133,15 +134,15 @@ template <> struct BlockLDS<1> {  // FP32: positions relative to the block origi
     double red[WAVES][64 * 6];
   };
 };
-template <> struct BlockLDS<0> {  // FP64: raw positions
-  BlockHdr h;
-  union {
-    struct {
-      double x[CAPB], y[CAPB], z[CAPB];
-    } t;
-    double red[WAVES][64 * 6];
-  };
+template <> struct BlockLDS<0> {  // FP64: raw positions, plus per entry the periodic image
+  BlockHdr h;                     // and the FP32 |q|^2 of the matrix-core pre-filter
+  double x[CAPB + QPAD], y[CAPB + QPAD], z[CAPB + QPAD];
+  float qn[CAPB + QPAD];
+  uint8_t img[CAPB + QPAD];       // (sx + 1) | (sy + 1) << 2 | (sz + 1) << 4: image shift s L
 };
+
+// Image code of a staged entry without a periodic shift.
+constexpr uint8_t IMG_NONE = 1 | (1 << 2) | (1 << 4);
 
 struct ForceOut {
   double fx, fy, fz;  // force on the lane's atom (lanes < n)
@@ -303,35 +304,63 @@ __device__ __forceinline__ void stage_issue(const DGeom& g, const uint32_t* ncnt
 
 // wrap: some staged cell of the block is a periodic image (its coordinates are shifted
 // by a box length); without it the shift is 0 and x + 0 = x exactly.
+// FP32 origin of a block: the column corner at the start of z0's aligned group of BZ
+// cells, so a pair's FP32 arithmetic depends on the cell only, not on how cells form
+// blocks.
+__device__ __forceinline__ void block_origin(const DGeom& g, int gx, int gy, int z0, double o[3]) {
+  o[0] = __dmul_rn((double)gx, g.l[0]);
+  o[1] = __dmul_rn((double)gy, g.l[1]);
+  o[2] = __dmul_rn((double)(z0 - z0 % BZ), g.l[2]);
+}
+
+// FP32 coordinate of a staged position: (x + s L) - o, rounded once to FP32.
+__device__ __forceinline__ float rel32(double x, int s, double L, double o) {
+  return (float)__dsub_rn(__dadd_rn(x, (double)s * L), o);
+}
+
+// wrap: some staged cell of the block is a periodic image (its coordinates are shifted
+// by a box length); without it every shift is 0.
 template <int PREC>
 __device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, BlockLDS<PREC>& L, int m,
                                           int p, double x, double y, double z, bool wrap) {
+  double o[3];
+  block_origin(g, R.gx, R.gy, R.z0, o);
   if constexpr (PREC == 1) {
-    // FP32 origin: the column corner at the start of z0's aligned group of BZ cells, so
-    // a pair's FP32 arithmetic depends on the cell only, not on how cells form blocks
-    const double ox = __dmul_rn((double)R.gx, g.l[0]), oy = __dmul_rn((double)R.gy, g.l[1]),
-                 oz = __dmul_rn((double)(R.z0 - R.z0 % BZ), g.l[2]);
     float qx, qy, qz;
     if (!wrap) {
-      qx = (float)__dsub_rn(x, ox);
-      qy = (float)__dsub_rn(y, oy);
-      qz = (float)__dsub_rn(z, oz);
+      qx = (float)__dsub_rn(x, o[0]);
+      qy = (float)__dsub_rn(y, o[1]);
+      qz = (float)__dsub_rn(z, o[2]);
     } else {
       int nx, ny, nz;
       staged_cell_xyz(R.gx, R.gy, R.z0, m, nx, ny, nz);
       const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
       const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
       const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
-      qx = (float)__dsub_rn(__dadd_rn(x, shx), ox);
-      qy = (float)__dsub_rn(__dadd_rn(y, shy), oy);
-      qz = (float)__dsub_rn(__dadd_rn(z, shz), oz);
+      qx = (float)__dsub_rn(__dadd_rn(x, shx), o[0]);
+      qy = (float)__dsub_rn(__dadd_rn(y, shy), o[1]);
+      qz = (float)__dsub_rn(__dadd_rn(z, shz), o[2]);
     }
     // w: |q|^2, the norm term of the matrix-core distance test
     L.q[p] = make_float4(qx, qy, qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
   } else {
-    L.t.x[p] = x;
-    L.t.y[p] = y;
-    L.t.z[p] = z;
+    // raw positions for the exact FP64 pair terms; the image code and the FP32 |q|^2
+    // give the pre-filter the FP32 coordinates the FP32 staging would hold (without an
+    // image x + 0 L = x exactly, so both forms agree)
+    int sx = 0, sy = 0, sz = 0;
+    if (wrap) {
+      int nx, ny, nz;
+      staged_cell_xyz(R.gx, R.gy, R.z0, m, nx, ny, nz);
+      sx = nx < 0 ? -1 : (nx >= g.G[0] ? 1 : 0);
+      sy = ny < 0 ? -1 : (ny >= g.G[1] ? 1 : 0);
+      sz = nz < 0 ? -1 : (nz >= g.G[2] ? 1 : 0);
+    }
+    const float qx = rel32(x, sx, g.L[0], o[0]), qy = rel32(y, sy, g.L[1], o[1]), qz = rel32(z, sz, g.L[2], o[2]);
+    L.x[p] = x;
+    L.y[p] = y;
+    L.z[p] = z;
+    L.qn[p] = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+    L.img[p] = (uint8_t)((sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4));
   }
 }
 
@@ -363,6 +392,7 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
     if (lane == 0) {
       L.h.nb = nb;
       L.h.wrap_col = R.gx == 0 || R.gx == g.G[0] - 1 || R.gy == 0 || R.gy == g.G[1] - 1;
+      if constexpr (PREC == 0) block_origin(g, R.gx, R.gy, R.z0, L.h.org);
     }
     if (lane < BLAYERS) {
       const int nz = R.z0 - 1 + lane;
@@ -370,8 +400,14 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
     }
     // far sentinels after the last staged atom: a pair-loop read past the end of the
     // list finds no partner in range
-    if constexpr (PREC == 1) {
-      if (lane < QPAD) L.q[stot + lane] = make_float4(FAR_Q, FAR_Q, FAR_Q, 3.0f * FAR_Q * FAR_Q);
+    if (lane < QPAD) {
+      if constexpr (PREC == 1) {
+        L.q[stot + lane] = make_float4(FAR_Q, FAR_Q, FAR_Q, 3.0f * FAR_Q * FAR_Q);
+      } else {
+        L.x[stot + lane] = L.y[stot + lane] = L.z[stot + lane] = (double)FAR_Q;
+        L.qn[stot + lane] = 3.0f * FAR_Q * FAR_Q;
+        L.img[stot + lane] = IMG_NONE;
+      }
     }
   }
   const bool wrap = R.gx == 0 || R.gx == g.G[0] - 1 || R.gy == 0 || R.gy == g.G[1] - 1 || R.z0 == 0 ||
@@ -558,129 +594,111 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, const 
   }
 }
 
-// FP64 pair forces of every atom of the cell of this wave in the staged block
-// (Algorithm 1, first loop; kernel md_v3a).  Each lane holds two atoms of the cell
-// (a and a + P, P = ceil(n/2)) and one of G candidate groups; lane (a, grp) visits
-// candidates grp, grp + G, ... of the cell's 27-cell window, so one LDS read serves two
-// pairs.  Group partials are added in group order: every atom's sum has a fixed order.
-// Whole workgroup (contains a barrier); waves without a cell only take part in it.
+// FP64 pair forces of every atom of the cell of wave w in the staged block (Algorithm 1,
+// first loop; kernel md_v3a), in the lane layout and with the matrix-core pre-filter of
+// the FP32 path: pass 1 rebuilds each entry's FP32 coordinates from its FP64 position,
+// image code and the block origin (the values the FP32 staging would hold) and marks a
+// superset of the pairs in range; pass 2 evaluates the marked pairs within the window
+// with the FP64 pair arithmetic on the raw positions (minimum image where the block
+// touches a periodic boundary), so every pair term and range decision is the one a
+// pair-by-pair FP64 loop makes.  Quarter partials are added in quarter order.
+// Wave-level (no barrier).
 template <bool ENERGY, bool COUNT>
-__device__ void block_force64(const DGeom& g, BlockLDS<0>& L, int w, ForceOut& o) {
+__device__ void block_force64(const DGeom& g, const BlockLDS<0>& L, int w, ForceOut& o) {
   const int lane = __lane_id();
+  const int col = lane & 15, quarter = lane >> 4;
   const int n_i = o.n;
-  const int total = o.total;
   const int ci = 9 * (w + 1) + 4;
   const int beg = L.h.pre[9 * w];
-  Acc<double> A, B;
-  acc_init(A);
-  acc_init(B);
-  int P = 1, G = 1;
-  if (n_i > 0) {
-    P = (n_i + 1) >> 1;
-    G = 64 / P;
-    if (G > 16) G = 16;
-    const int ia = lane % P;
-    const int grp = lane / P;
-    const int ib_ = ia + P;
-    const bool has_b = ib_ < n_i;
-    const int f0 = grp < G ? beg + grp : beg + total;
-    const int fe = beg + total;
-    const int si = L.h.pre[ci];  // own atoms in the staged list
-    const double ax = L.t.x[si + ia], ay = L.t.y[si + ia], az = L.t.z[si + ia];
-    const double bx = has_b ? L.t.x[si + ib_] : 1e300, by = has_b ? L.t.y[si + ib_] : 1e300,
-                 bz = has_b ? L.t.z[si + ib_] : 1e300;
-    const bool wrap = L.h.wrap_col || L.h.wrap_layer[w] || L.h.wrap_layer[w + 2];
-    if (!wrap) {
-      // no periodic neighbour: the raw difference is the minimum image of every pair
-      // that can be in range
-#pragma unroll 2
-      for (int f = f0; f < fe; f += G) {
-        const double xj = L.t.x[f], yj = L.t.y[f], zj = L.t.z[f];
-        pair64<ENERGY, COUNT, false>(g, ax, ay, az, xj, yj, zj, A);
-        pair64<ENERGY, COUNT, false>(g, bx, by, bz, xj, yj, zj, B);
+  const int fe = beg + o.total;
+  const int si = L.h.pre[ci];  // own atoms in the staged list
+  const int ntile = __builtin_amdgcn_readfirstlane((o.total + 15) >> 4);
+  const bool wrap = L.h.wrap_col || L.h.wrap_layer[w] || L.h.wrap_layer[w + 2];
+  // the component this lane supplies to the matrix ops (3: |q|^2)
+  const int kc = quarter < 3 ? quarter : 2;
+  const double* X = kc == 0 ? L.x : (kc == 1 ? L.y : L.z);
+  const double Lk = g.L[kc], ok = L.h.org[kc];
+  auto comp32 = [&](int f) {
+    if (quarter == 3) return L.qn[f];
+    const int s = (((int)L.img[f] >> (2 * kc)) & 3) - 1;
+    return rel32(X[f], s, Lk, ok);
+  };
+  for (int u = 0; 16 * u < n_i; u++) {
+    const int a = 16 * u + col;
+    const bool real = a < n_i;
+    const int ia = si + (real ? a : 0);
+    const float qc = comp32(ia);
+    const float bop = real ? (quarter == 3 ? 1.0f : -2.0f * qc) : 0.0f;
+    const float cacc = real ? L.qn[ia] - g.rc2_pre_f : 1e30f;
+    const mfma_f4 cop = {cacc, cacc, cacc, cacc};
+    const double xi = L.x[ia], yi = L.y[ia], zi = L.z[ia];
+    Acc<double> A;
+    acc_init(A);
+    const int r0 = beg + (col >> 2) + 4 * (col & 3);  // row col of tile 0 (as in the FP32 path)
+    auto mark = [&](unsigned m, float av) {
+      asm volatile("" : "+v"(av) : "v"(m));
+      const mfma_f4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bop, cop, 0, 0, 0);
+      m = __builtin_amdgcn_alignbit(m, __float_as_uint(d[0]), 31);
+      m = __builtin_amdgcn_alignbit(m, __float_as_uint(d[1]), 31);
+      m = __builtin_amdgcn_alignbit(m, __float_as_uint(d[2]), 31);
+      return __builtin_amdgcn_alignbit(m, __float_as_uint(d[3]), 31);
+    };
+    for (int tb = 0; tb < ntile; tb += 8) {
+      const int cn = min(8, ntile - tb);
+      unsigned m = 0u;
+      if (cn == 8) {
+        float av[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) av[t] = comp32(r0 + 16 * (tb + t));
+#pragma unroll
+        for (int t = 0; t < 8; t++) m = mark(m, av[t]);
+      } else {
+        for (int t = 0; t < cn; t++) m = mark(m, comp32(r0 + 16 * (tb + t)));
+        m <<= 32 - 4 * cn;
       }
-    } else {
-      for (int f = f0; f < fe; f += G) {
-        const double xj = L.t.x[f], yj = L.t.y[f], zj = L.t.z[f];
-        pair64<ENERGY, COUNT, true>(g, ax, ay, az, xj, yj, zj, A);
-        pair64<ENERGY, COUNT, true>(g, bx, by, bz, xj, yj, zj, B);
-      }
+      // bit b marks candidate 4 b + quarter of the batch; candidates at or past the end
+      // of the window are dropped (with raw positions a periodic copy of a window cell
+      // there could otherwise be counted twice)
+      m = __builtin_bitreverse32(m);
+      const int fb = beg + 16 * tb + quarter;
+      const int nvalid = (fe - fb + 3) >> 2;
+      if (nvalid < 32) m &= nvalid > 0 ? (1u << nvalid) - 1u : 0u;
+      auto pairs = [&](auto wrap_c) {
+        constexpr bool WRAP = decltype(wrap_c)::value;
+        while (m) {
+          const int b1 = __ffs(m) - 1;
+          m &= m - 1u;
+          const bool two = m != 0u;
+          const int b2 = __ffs(m) - 1;
+          m &= m - 1u;
+          const int f1 = fb + 4 * b1, f2 = two ? fb + 4 * b2 : ia;
+          pair64<ENERGY, COUNT, WRAP>(g, xi, yi, zi, L.x[f1], L.y[f1], L.z[f1], A);
+          pair64<ENERGY, COUNT, WRAP>(g, xi, yi, zi, L.x[f2], L.y[f2], L.z[f2], A);
+        }
+      };
+      if (wrap)
+        pairs(std::true_type());
+      else
+        pairs(std::false_type());
     }
-  }
-  // every wave is done with the staged positions; the same LDS now holds the partials
-  __syncthreads();
-  if (n_i > 0) {
-    // Forces: both atoms' group partials per lane (three double2), summed in group order,
-    // then handed to the lane of each atom.
-    double2* r2 = reinterpret_cast<double2*>(L.red[w]);
-    r2[3 * lane] = make_double2(A.fx, A.fy);
-    r2[3 * lane + 1] = make_double2(A.fz, B.fx);
-    r2[3 * lane + 2] = make_double2(B.fy, B.fz);
-    wave_sync();
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0;
-    if (lane < P) {
-      for (int q = 0; q < G; q++) {
-        const int j = 3 * (lane + q * P);
-        const double2 u = r2[j], v = r2[j + 1], t = r2[j + 2];
-        s0 += u.x;
-        s1 += u.y;
-        s2 += v.x;
-        s3 += v.y;
-        s4 += t.x;
-        s5 += t.y;
-      }
-    }
-    wave_sync();
-    if (lane < P) {
-      r2[2 * lane] = make_double2(s0, s1);
-      r2[2 * lane + 1] = make_double2(s2, 0.0);
-      if (lane + P < n_i) {
-        r2[2 * (lane + P)] = make_double2(s3, s4);
-        r2[2 * (lane + P) + 1] = make_double2(s5, 0.0);
-      }
-    }
-    wave_sync();
-    if (lane < n_i) {
-      const double2 u = r2[2 * lane], v = r2[2 * lane + 1];
-      o.fx = u.x;
-      o.fy = u.y;
-      o.fz = v.x;
+    // quarter partials of column col, added in quarter order; lane 16 u + col keeps them
+    const double sx = ((__shfl(A.fx, col) + __shfl(A.fx, col + 16)) + __shfl(A.fx, col + 32)) + __shfl(A.fx, col + 48);
+    const double sy = ((__shfl(A.fy, col) + __shfl(A.fy, col + 16)) + __shfl(A.fy, col + 32)) + __shfl(A.fy, col + 48);
+    const double sz = ((__shfl(A.fz, col) + __shfl(A.fz, col + 16)) + __shfl(A.fz, col + 32)) + __shfl(A.fz, col + 48);
+    const bool keep = quarter == u && real;
+    if (keep) {
+      o.fx = sx;
+      o.fy = sy;
+      o.fz = sz;
     }
     if constexpr (ENERGY || COUNT) {
-      // energy, virial and partner count (sampled steps, count mode): group order
-      double* red = L.red[w];
-      double sa[3] = {0.0, 0.0, 0.0}, sb[3] = {0.0, 0.0, 0.0};
-      for (int h = 0; h < 2; h++) {
-        const Acc<double>& X = h == 0 ? A : B;
-        wave_sync();
-        red[lane * 3 + 0] = X.u;
-        red[lane * 3 + 1] = X.w;
-        red[lane * 3 + 2] = (double)X.pc;
-        wave_sync();
-        if (lane < P) {
-          double* sv = h == 0 ? sa : sb;
-          for (int q = 0; q < G; q++) {
-            const double* r = red + (lane + q * P) * 3;
-#pragma unroll
-            for (int v = 0; v < 3; v++) sv[v] += r[v];
-          }
-        }
-      }
-      wave_sync();
-      if (lane < P) {
-#pragma unroll
-        for (int v = 0; v < 3; v++) red[lane * 3 + v] = sa[v];
-        if (lane + P < n_i) {
-#pragma unroll
-          for (int v = 0; v < 3; v++) red[(lane + P) * 3 + v] = sb[v];
-        }
-      }
-      wave_sync();
-      if (lane < n_i) {
-        const double* r = red + lane * 3;
-        o.uh = 0.5 * r[0];
-        o.wh = 0.5 * r[1];
-        o.pc = (unsigned)r[2];
+      const double su = ((__shfl(A.u, col) + __shfl(A.u, col + 16)) + __shfl(A.u, col + 32)) + __shfl(A.u, col + 48);
+      const double sw = ((__shfl(A.w, col) + __shfl(A.w, col + 16)) + __shfl(A.w, col + 32)) + __shfl(A.w, col + 48);
+      const unsigned sp = __shfl(A.pc, col) + __shfl(A.pc, col + 16) + __shfl(A.pc, col + 32) + __shfl(A.pc, col + 48);
+      if (keep) {
+        o.uh = 0.5 * su;
+        o.wh = 0.5 * sw;
+        o.pc = sp;
       }
     }
   }
@@ -1397,7 +1415,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void pe
   persistent_body<1, false, false>(la);
 }
 __global__ __launch_bounds__(WG) void persistent_f32_full(LaunchArgs la) { persistent_body<1, true, false>(la); }
-__global__ __launch_bounds__(WG) void persistent_f64_lean(LaunchArgs la) { persistent_body<0, false, false>(la); }
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void persistent_f64_lean(LaunchArgs la) { persistent_body<0, false, false>(la); }
 __global__ __launch_bounds__(WG) void persistent_f64_full(LaunchArgs la) { persistent_body<0, true, false>(la); }
 __global__ __launch_bounds__(WG) void persistent_f32_lean_nvt(LaunchArgs la) { persistent_body<1, false, true>(la); }
 __global__ __launch_bounds__(WG) void persistent_f32_full_nvt(LaunchArgs la) { persistent_body<1, true, true>(la); }
