@@ -127,12 +127,11 @@ struct BlockHdr {
 };
 
 template <int PREC> struct BlockLDS;
+constexpr int GMASKS = 4;  // pre-filter masks kept per lane for the guard-band pass (32 tiles)
 template <> struct BlockLDS<1> {  // FP32: positions relative to the block origin, |q|^2
   BlockHdr h;
-  union {
-    float4 q[CAPB + QPAD];
-    double red[WAVES][64 * 6];
-  };
+  float4 q[CAPB + QPAD];
+  unsigned gmask[WAVES][GMASKS][64];  // each wave's pass-1 marks of its current atom batch
 };
 template <> struct BlockLDS<0> {  // FP64: raw positions, plus per entry the periodic image
   BlockHdr h;                     // and the FP32 |q|^2 of the matrix-core pre-filter
@@ -182,11 +181,13 @@ __device__ __forceinline__ unsigned prefilter32(const float4& qi, const float4& 
   return __builtin_amdgcn_alignbit(m, __float_as_uint(d), 31);
 }
 
-// FP32 pair term of a pre-filtered pair (Algorithm 1 loop body), the range decision
-// and arithmetic of pair32.  Returns true for a guard-band pair (decided again in FP64).
+// FP32 pair term of a pre-filtered pair (Algorithm 1 loop body): the range decision and
+// arithmetic of a pair-by-pair FP32 loop.  Returns rb - lo_bits (unsigned, rb = bits of
+// r2 minus 1): below hi_bits - lo_bits exactly for a guard-band pair, which is then
+// decided again in FP64; pairs in range, out of range and the self pair give more.
 template <bool ENERGY, bool COUNT>
-__device__ __forceinline__ bool pair32_in(const float4& qi, const float4& q, unsigned lo_bits, unsigned hi_bits,
-                                          float ucf, Acc<float>& a) {
+__device__ __forceinline__ unsigned pair32_in(const float4& qi, const float4& q, unsigned lo_bits, float ucf,
+                                              Acc<float>& a) {
   const float dx = qi.x - q.x, dy = qi.y - q.y, dz = qi.z - q.z;
   const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
   const unsigned rb = __float_as_uint(r2) - 1u;
@@ -203,7 +204,7 @@ __device__ __forceinline__ bool pair32_in(const float4& qi, const float4& q, uns
     a.w += in ? (double)(24.0f * ir6 * fmaf(2.0f, ir6, -1.0f)) : 0.0;
   }
   if (COUNT) a.pc += in ? 1u : 0u;
-  return !in & (rb < hi_bits);
+  return rb - lo_bits;
 }
 
 // The same FP32 pair term, added unconditionally (guard-band pairs found in range).
@@ -470,7 +471,7 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 // An atom's four quarter partials are added in quarter order, so every sum has a fixed
 // order.  Wave-level (no barrier).
 template <bool ENERGY, bool COUNT>
-__device__ void block_force32(const DGeom& g, const unsigned char* cells, const BlockLDS<1>& L, int w,
+__device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockLDS<1>& L, int w,
                               ForceOut& o) {
   const int lane = __lane_id();
   const int col = lane & 15, quarter = lane >> 4;
@@ -495,7 +496,7 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, const 
     const mfma_f4 cop = {cacc, cacc, cacc, cacc};
     Acc<float> A;
     acc_init(A);
-    bool flag = false;
+    unsigned bmin = 0xffffffffu;  // least rb - lo_bits of the lane's pairs (guard band test)
     // row i = 4 r + s of a tile is candidate s + 4 r of it (lane quarter s then holds
     // every fourth candidate); the lane supplies component `quarter` of row `col`
     const float* ap = Lf + 4 * (beg + (col >> 2) + 4 * (col & 3)) + quarter;
@@ -527,6 +528,7 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, const 
       // after the reversal, bit b = 4 t + r marks row 4 quarter + r of tile t, i.e.
       // candidate 16 t + quarter + 4 r = 4 b + quarter of the batch
       m = __builtin_bitreverse32(m);
+      if (tb < 8 * GMASKS) L.gmask[w][tb >> 3][lane] = m;
       const int fb = beg + 16 * tb + quarter;
       // the marked pairs two at a time, in a fixed order (lowest bit first); a missing
       // second pair is the self pair (r2 = 0: excluded exactly like every self pair)
@@ -538,36 +540,53 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, const 
         m &= m - 1u;
         const float4 q1 = L.q[fb + 4 * b1];
         const float4 q2 = L.q[two ? fb + 4 * b2 : si + a];
-        flag |= pair32_in<ENERGY, COUNT>(qa, q1, lo_bits, hi_bits, g.uc_f, A);
-        flag |= pair32_in<ENERGY, COUNT>(qa, q2, lo_bits, hi_bits, g.uc_f, A);
+        const unsigned t1 = pair32_in<ENERGY, COUNT>(qa, q1, lo_bits, g.uc_f, A);
+        const unsigned t2 = pair32_in<ENERGY, COUNT>(qa, q2, lo_bits, g.uc_f, A);
+        bmin = min(bmin, min(t1, t2));
       }
     }
-    // guard band: decide those pairs in FP64 exactly as the FP64 path would
+    // guard band: decide those pairs in FP64 exactly as the FP64 path would.  Every pair
+    // in the band was marked, so the lane visits its marked candidates again (from the
+    // saved masks; a window beyond their 32 tiles is scanned in full).
+    const bool flag = bmin < hi_bits - lo_bits;
     if (__ballot(flag) && flag) {
       const double* iblk = cblk(cells, o.c);
       const double xi = iblk[a], yi = iblk[CELL_CAP + a], zi = iblk[2 * CELL_CAP + a];
-      for (int t = 0; t < ntile; t++) {
-        for (int r = 0; r < 4; r++) {
-          const int f = beg + 16 * t + quarter + 4 * r;
-          if (f >= fe) continue;
-          const float4 q = L.q[f];
-          const float dx = qa.x - q.x, dy = qa.y - q.y, dz = qa.z - q.z;
-          const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-          const unsigned rb = __float_as_uint(r2) - 1u;
-          if (rb >= lo_bits && rb < hi_bits) {
-            // staged cell of entry f: the last one whose first entry is at or before f
-            int sm = 0;
+      auto guard = [&](int f) {
+        const float4 q = L.q[f];
+        const float dx = qa.x - q.x, dy = qa.y - q.y, dz = qa.z - q.z;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const unsigned rb = __float_as_uint(r2) - 1u;
+        if (rb >= lo_bits && rb < hi_bits) {
+          // staged cell of entry f: the last one whose first entry is at or before f
+          int sm = 0;
 #pragma unroll
-            for (int step = 32; step >= 1; step >>= 1)
-              if (sm + step < BCELLS && L.h.pre[sm + step] <= f) sm += step;
-            const double* jb = cblk(cells, L.h.nb_cell[sm]);
-            const int k = f - L.h.pre[sm];
-            const double ex = min_img(__dsub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
-            const double ey = min_img(__dsub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
-            const double ez = min_img(__dsub_rn(zi, jb[2 * CELL_CAP + k]), g.L[2], g.halfL[2]);
-            if (r2_exact(ex, ey, ez) <= g.rc2) pair32_add<ENERGY, COUNT>(dx, dy, dz, r2, g.uc_f, A);
+          for (int step = 32; step >= 1; step >>= 1)
+            if (sm + step < BCELLS && L.h.pre[sm + step] <= f) sm += step;
+          const double* jb = cblk(cells, L.h.nb_cell[sm]);
+          const int k = f - L.h.pre[sm];
+          const double ex = min_img(__dsub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
+          const double ey = min_img(__dsub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
+          const double ez = min_img(__dsub_rn(zi, jb[2 * CELL_CAP + k]), g.L[2], g.halfL[2]);
+          if (r2_exact(ex, ey, ez) <= g.rc2) pair32_add<ENERGY, COUNT>(dx, dy, dz, r2, g.uc_f, A);
+        }
+      };
+      if (ntile <= 8 * GMASKS) {
+        for (int bi = 0; 8 * bi < ntile; bi++) {
+          unsigned m = L.gmask[w][bi][lane];
+          const int fb = beg + 128 * bi + quarter;
+          while (m) {
+            const int f = fb + 4 * (__ffs(m) - 1);
+            m &= m - 1u;
+            if (f < fe) guard(f);
           }
         }
+      } else {
+        for (int t = 0; t < ntile; t++)
+          for (int r = 0; r < 4; r++) {
+            const int f = beg + 16 * t + quarter + 4 * r;
+            if (f < fe) guard(f);
+          }
       }
     }
     // quarter partials of column col, added in quarter order; lane 16 u + col keeps them
