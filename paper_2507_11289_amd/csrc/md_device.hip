@@ -172,15 +172,6 @@ template <class R> __device__ __forceinline__ R force_factor(R ir2, R ir6) {
   return (ir6 * (ir6 * (R)48 - (R)24)) * ir2;
 }
 
-// Pre-filter of one pair: shifts bit (r2 < rc2_pre) into the mask.  The threshold is
-// folded into the FMA chain; the sign of r2 - rc2_pre is the bit (a superset test:
-// the exact decision follows in pair32_in).
-__device__ __forceinline__ unsigned prefilter32(const float4& qi, const float4& q, float pre, unsigned m) {
-  const float dx = qi.x - q.x, dy = qi.y - q.y, dz = qi.z - q.z;
-  const float d = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, -pre)));
-  return __builtin_amdgcn_alignbit(m, __float_as_uint(d), 31);
-}
-
 // FP32 pair term of a pre-filtered pair (Algorithm 1 loop body): the range decision and
 // arithmetic of a pair-by-pair FP32 loop.  Returns rb - lo_bits (unsigned, rb = bits of
 // r2 minus 1): below hi_bits - lo_bits exactly for a guard-band pair, which is then
@@ -466,8 +457,10 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 //     (x, y, z, |q|^2), atom columns (-2x, -2y, -2z, 1) and accumulator |q_a|^2 - pre
 //     gives r2 - pre for all 256 pairs; its error is far below the margin of pre over
 //     the guard band, so the sign bits mark a superset of the pairs in range.
-//   Pass 2 (vector ALU): the marked pairs in slot order, with the exact FP32 arithmetic
-//     and range decision of a pair-by-pair loop; guard-band pairs are decided in FP64.
+//   Pass 2 (vector ALU): the marked pairs two at a time in a fixed order, with the exact
+//     FP32 arithmetic and range decision of a pair-by-pair loop; a running minimum of
+//     rb - lo_bits tells whether any pair fell in the guard band, and those pairs are
+//     then decided in FP64 (revisiting the lane's marked candidates from saved masks).
 // An atom's four quarter partials are added in quarter order, so every sum has a fixed
 // order.  Wave-level (no barrier).
 template <bool ENERGY, bool COUNT>
