@@ -35,17 +35,27 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ double* cblk(unsigned char* base, int c) {
-  return reinterpret_cast<double*>(base + (size_t)c * CELL_BYTES);
+// Device-memory pointers in the global address space.  The buffers reach the kernels
+// as generic pointers (inside the run arguments), which would make every access a flat
+// one: flat accesses count against the LDS counter as well, so each LDS wait would also
+// wait for all outstanding cell loads and stores.
+#define GLOBAL __attribute__((address_space(1)))
+typedef GLOBAL double gdouble;
+typedef GLOBAL uint32_t guint32;
+template <class T> __device__ __forceinline__ GLOBAL T* gptr(T* p) { return (GLOBAL T*)p; }
+template <class T> __device__ __forceinline__ const GLOBAL T* gptr(const T* p) { return (const GLOBAL T*)p; }
+
+__device__ __forceinline__ gdouble* cblk(unsigned char* base, int c) {
+  return (gdouble*)(base + (size_t)c * CELL_BYTES);
 }
-__device__ __forceinline__ const double* cblk(const unsigned char* base, int c) {
-  return reinterpret_cast<const double*>(base + (size_t)c * CELL_BYTES);
+__device__ __forceinline__ const gdouble* cblk(const unsigned char* base, int c) {
+  return (const gdouble*)(base + (size_t)c * CELL_BYTES);
 }
-__device__ __forceinline__ uint32_t* cids(double* b) {
-  return reinterpret_cast<uint32_t*>(b + CELL_DOUBLES);
+__device__ __forceinline__ guint32* cids(gdouble* b) {
+  return (guint32*)(b + CELL_DOUBLES);
 }
-__device__ __forceinline__ const uint32_t* cids(const double* b) {
-  return reinterpret_cast<const uint32_t*>(b + CELL_DOUBLES);
+__device__ __forceinline__ const guint32* cids(const gdouble* b) {
+  return (const guint32*)(b + CELL_DOUBLES);
 }
 
 __device__ __forceinline__ unsigned ld_relaxed(const uint32_t* p) {
@@ -115,6 +125,7 @@ constexpr int BCELLS = 9 * BLAYERS;     // staged cells
 constexpr int CAPB = 27 * CELL_CAP;     // staged atoms at most (one full neighbourhood)
 constexpr int QPAD = 16;                // far sentinels after the staged atoms (FP32)
 constexpr float FAR_Q = 1e15f;          // sentinel coordinate: far from everything, |q|^2 finite
+constexpr int FAR_SLOT = CAPB + QPAD - 1;  // always a far sentinel (FP32): the stand-in pair
 
 struct BlockHdr {
   int nb_cell[BCELLS];     // global cell of staged cell m
@@ -181,8 +192,10 @@ __device__ __forceinline__ unsigned pair32_in(const float4& qi, const float4& q,
                                               Acc<float>& a) {
   const float dx = qi.x - q.x, dy = qi.y - q.y, dz = qi.z - q.z;
   const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-  const unsigned rb = __float_as_uint(r2) - 1u;
-  const bool in = rb < lo_bits;
+  // u = rb - lo_bits (mod 2^32) in one subtraction; rb < lo_bits (in range) exactly when
+  // u > ~lo_bits, which r2 = 0 (u = ~lo_bits) is not
+  const unsigned u = __float_as_uint(r2) - (lo_bits + 1u);
+  const bool in = u > ~lo_bits;
   const float ir2 = __builtin_amdgcn_rcpf(r2);
   const float ir6 = ir2 * ir2 * ir2;
   float fr = force_factor(ir2, ir6);
@@ -195,7 +208,7 @@ __device__ __forceinline__ unsigned pair32_in(const float4& qi, const float4& q,
     a.w += in ? (double)(24.0f * ir6 * fmaf(2.0f, ir6, -1.0f)) : 0.0;
   }
   if (COUNT) a.pc += in ? 1u : 0u;
-  return rb - lo_bits;
+  return u;
 }
 
 // The same FP32 pair term, added unconditionally (guard-band pairs found in range).
@@ -291,7 +304,7 @@ __device__ __forceinline__ void stage_issue(const DGeom& g, const uint32_t* ncnt
     nc = global_cell(g, nx, ny, nz);
   }
   R.nc = nc;
-  R.cnt = lane < ncs ? (int)ncnt[nc] : 0;
+  R.cnt = lane < ncs ? (int)gptr(ncnt)[nc] : 0;
 }
 
 // wrap: some staged cell of the block is a periodic image (its coordinates are shifted
@@ -395,6 +408,7 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
     if (lane < QPAD) {
       if constexpr (PREC == 1) {
         L.q[stot + lane] = make_float4(FAR_Q, FAR_Q, FAR_Q, 3.0f * FAR_Q * FAR_Q);
+        if (lane == 0) L.q[FAR_SLOT] = make_float4(FAR_Q, FAR_Q, FAR_Q, 3.0f * FAR_Q * FAR_Q);
       } else {
         L.x[stot + lane] = L.y[stot + lane] = L.z[stot + lane] = (double)FAR_Q;
         L.qn[stot + lane] = 3.0f * FAR_Q * FAR_Q;
@@ -420,7 +434,7 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
       const int cm = __shfl(R.nc, m & 63);
       mm[r] = m;
       if (f < stot) {
-        const double* jb = cblk(cells, cm);
+        const gdouble* jb = cblk(cells, cm);
         x[r] = jb[k];
         y[r] = jb[CELL_CAP + k];
         z[r] = jb[2 * CELL_CAP + k];
@@ -524,7 +538,8 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
       if (tb < 8 * GMASKS) L.gmask[w][tb >> 3][lane] = m;
       const int fb = beg + 16 * tb + quarter;
       // the marked pairs two at a time, in a fixed order (lowest bit first); a missing
-      // second pair is the self pair (r2 = 0: excluded exactly like every self pair)
+      // second pair is a far sentinel (out of range and outside the band: it adds
+      // exactly nothing)
       while (m) {
         const int b1 = __ffs(m) - 1;
         m &= m - 1u;
@@ -532,7 +547,7 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
         const int b2 = __ffs(m) - 1;
         m &= m - 1u;
         const float4 q1 = L.q[fb + 4 * b1];
-        const float4 q2 = L.q[two ? fb + 4 * b2 : si + a];
+        const float4 q2 = L.q[two ? fb + 4 * b2 : FAR_SLOT];
         const unsigned t1 = pair32_in<ENERGY, COUNT>(qa, q1, lo_bits, g.uc_f, A);
         const unsigned t2 = pair32_in<ENERGY, COUNT>(qa, q2, lo_bits, g.uc_f, A);
         bmin = min(bmin, min(t1, t2));
@@ -543,7 +558,7 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
     // saved masks; a window beyond their 32 tiles is scanned in full).
     const bool flag = bmin < hi_bits - lo_bits;
     if (__ballot(flag) && flag) {
-      const double* iblk = cblk(cells, o.c);
+      const gdouble* iblk = cblk(cells, o.c);
       const double xi = iblk[a], yi = iblk[CELL_CAP + a], zi = iblk[2 * CELL_CAP + a];
       auto guard = [&](int f) {
         const float4 q = L.q[f];
@@ -556,7 +571,7 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
 #pragma unroll
           for (int step = 32; step >= 1; step >>= 1)
             if (sm + step < BCELLS && L.h.pre[sm + step] <= f) sm += step;
-          const double* jb = cblk(cells, L.h.nb_cell[sm]);
+          const gdouble* jb = cblk(cells, L.h.nb_cell[sm]);
           const int k = f - L.h.pre[sm];
           const double ex = min_img(__dsub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
           const double ey = min_img(__dsub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
@@ -758,15 +773,15 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
   int x = b;
   issue(x, R);
   while (true) {
-    __syncthreads();  // every wave is done with the previous block's LDS
-    const int nb = stage_commit<PREC>(g, cells, R, L);
     ForceOut o;
     if (OWN) {
+      // issued before the block is staged (the capacity check may still drop this cell;
+      // the data is then unused), so it has arrived before the pair loop needs registers
       const int ci = 9 * (w + 1) + 4;
-      const int n_own = w < nb ? __shfl(R.cnt, ci) : 0;
+      const int n_own = w < R.nb_max ? __shfl(R.cnt, ci) : 0;
       const int c_own = __shfl(R.nc, ci);
       if (lane < n_own) {
-        const double* ib = cblk(cells, c_own);
+        const gdouble* ib = cblk(cells, c_own);
 #pragma unroll
         for (int d = 0; d < 3; d++) {
           o.x[d] = ib[d * CELL_CAP + lane];
@@ -775,6 +790,8 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
         o.id = cids(ib)[lane];
       }
     }
+    __syncthreads();  // every wave is done with the previous block's LDS
+    const int nb = stage_commit<PREC>(g, cells, R, L);
     block_force<PREC, ENERGY, COUNT>(g, cells, L, o);
     x += nb;
     const bool more = x < e;
@@ -820,7 +837,7 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first
   const int c = o.c;
   if (c < 0) return;
   if (o.n == 0) {
-    if (lane == 0) ra.ncnt[dst][c] = 0u;
+    if (lane == 0) gptr(ra.ncnt[dst])[c] = 0u;
     return;
   }
   const bool own = lane < o.n;
@@ -877,12 +894,12 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first
                                           __builtin_amdgcn_mbcnt_lo((unsigned)sm, 0u));
   } else if (ok) {
     const unsigned old =
-        __hip_atomic_fetch_add(ra.nin[dst] + dest, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gptr(ra.nin[dst]) + dest, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old < (unsigned)CELL_CAP) slot = CELL_CAP - 1 - (int)old;
     else raise_error(ra.err, abort_flag, ERR_CAPACITY);
   }
   if (slot >= 0) {
-    double* ob = cblk(ra.cells[dst], dest);
+    gdouble* ob = cblk(ra.cells[dst], dest);
 #pragma unroll
     for (int d = 0; d < 3; d++) {
       ob[d * CELL_CAP + slot] = xn[d];
@@ -890,7 +907,7 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first
     }
     cids(ob)[slot] = id;
   }
-  if (lane == 0) ra.ncnt[dst][c] = (uint32_t)__popcll(sm);
+  if (lane == 0) gptr(ra.ncnt[dst])[c] = (uint32_t)__popcll(sm);
   acc.left += (unsigned)__popcll(__ballot(ok && dir == 1));
   acc.right += (unsigned)__popcll(__ballot(ok && dir == 2));
 }
@@ -939,8 +956,8 @@ __device__ void p2_force_tail(const RunArgs& ra, const ForceOut& o, int src, int
 __device__ void cell_sort_wave(unsigned char* cells, int c, int n_low, int n_high) {
   const int lane = __lane_id();
   const int n = n_low + n_high;
-  double* p = cblk(cells, c);
-  uint32_t* ids = cids(p);
+  gdouble* p = cblk(cells, c);
+  guint32* ids = cids(p);
   const bool act = lane < n;
   const int from = lane < n_low ? lane : CELL_CAP - 1 - (lane - n_low);
   double v[6];
@@ -974,14 +991,14 @@ __device__ void p1_range(const RunArgs& ra, int b, int e, int dst, int wave, uin
     const int c = base + lane;
     unsigned n_stay = 0, n_in = 0;
     if (c < e) {
-      n_stay = ra.ncnt[dst][c];
-      n_in = ra.nin[dst][c];
-      ra.nin[src][c] = 0u;
+      n_stay = gptr(ra.ncnt[dst])[c];
+      n_in = gptr(ra.nin[dst])[c];
+      gptr(ra.nin[src])[c] = 0u;
       if (n_stay + n_in > (unsigned)CELL_CAP) {
         raise_error(ra.err, abort_flag, ERR_CAPACITY);
         n_in = 0;
       }
-      if (n_in) ra.ncnt[dst][c] = n_stay + n_in;
+      if (n_in) gptr(ra.ncnt[dst])[c] = n_stay + n_in;
     }
     unsigned long long dirty = __ballot(n_in != 0);
     while (dirty) {
@@ -1171,7 +1188,7 @@ __device__ void run_p2b_item(const RunArgs& ra, const Item& it, double* s_lam, u
   for (int c = cbase + b + wave; c < cbase + e; c += WAVES) {
     ForceOut o;
     o.c = c;
-    o.n = (int)ra.ncnt[src][c];
+    o.n = (int)gptr(ra.ncnt[src])[c];
     o.total = 0;
     o.pc = 0;
     o.uh = o.wh = 0.0;
@@ -1181,7 +1198,7 @@ __device__ void run_p2b_item(const RunArgs& ra, const Item& it, double* s_lam, u
       o.fx = fb[lane];
       o.fy = fb[CELL_CAP + lane];
       o.fz = fb[2 * CELL_CAP + lane];
-      const double* ib = cblk(ra.cells[src], c);
+      const gdouble* ib = cblk(ra.cells[src], c);
 #pragma unroll
       for (int d = 0; d < 3; d++) {
         o.x[d] = ib[d * CELL_CAP + lane];
@@ -1488,7 +1505,7 @@ __global__ void load_scatter_kernel(DGeom g, const double* pos, const double* ve
     const int c = global_cell(g, gc[0], gc[1], gc[2]);
     const unsigned slot = atomicAdd(ncnt + c, 1u);
     if (slot < (unsigned)CELL_CAP) {
-      double* b = cblk(cells, c);
+      gdouble* b = cblk(cells, c);
       for (int d = 0; d < 3; d++) {
         b[d * CELL_CAP + slot] = pos[3 * i + d];
         b[(3 + d) * CELL_CAP + slot] = vel[3 * i + d];
@@ -1534,7 +1551,7 @@ __global__ __launch_bounds__(WG) void sync_kernel(DGeom g, const unsigned char* 
   const int e = min(g.cps, b + SYNC_CELLS);
   for_blocks<PREC, true, false, false>(g, cells, ncnt, slice, b, e, L, [&](const ForceOut& o) {
     if (o.c >= 0 && lane < o.n) {
-      const double* ib = cblk(cells, o.c);
+      const gdouble* ib = cblk(cells, o.c);
       const uint32_t id = cids(ib)[lane];
       const double F[3] = {o.fx, o.fy, o.fz};
       double vf[3];
