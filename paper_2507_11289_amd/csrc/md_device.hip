@@ -59,7 +59,7 @@ __device__ __forceinline__ const guint32* cids(const gdouble* b) {
 }
 
 __device__ __forceinline__ unsigned ld_relaxed(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void raise_error(uint32_t* err, uint32_t* abort_flag, uint32_t bits) {
@@ -1276,14 +1276,14 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
   if (nvt && it.phase == 0) {
     // thermostat: the slice's integrate items wait for all of its force items
     const unsigned needk = (unsigned)ra.nch * (unsigned)(it.k + 1);
-    const unsigned old = __hip_atomic_fetch_add(ra.cntK + it.slice, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned old = __hip_atomic_fetch_add(gptr(ra.cntK) + it.slice, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old + 1u != needk) return;
     // the completing count: see every counted item's results, then publish the pushes
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
     const unsigned long long base =
-        __hip_atomic_fetch_add(la.q_tail, (unsigned long long)ra.nch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gptr(la.q_tail), (unsigned long long)ra.nch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int ch = 0; ch < ra.nch; ch++)
-      __hip_atomic_store(la.q + base + ch, enc_item(it.run, it.k, 2, it.slice, ch), __ATOMIC_RELAXED,
+      __hip_atomic_store(gptr(la.q) + base + ch, enc_item(it.run, it.k, 2, it.slice, ch), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
@@ -1294,7 +1294,7 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
   uint32_t* cnt = update ? ra.cntF : ra.cntA;
   for (int d = -1; d <= 1; d++) {
     const int j = (it.slice + d + S) % S;
-    const unsigned old = __hip_atomic_fetch_add(cnt + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned old = __hip_atomic_fetch_add(gptr(cnt) + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old + 1u != need) continue;
     // the completing count: see every counted item's results, then publish the pushes
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
@@ -1309,9 +1309,9 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
     }
     const int nq = phase == 1 ? ra.nchA : ra.nch;
     const unsigned long long base =
-        __hip_atomic_fetch_add(la.q_tail, (unsigned long long)nq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gptr(la.q_tail), (unsigned long long)nq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int ch = 0; ch < nq; ch++)
-      __hip_atomic_store(la.q + base + ch, enc_item(it.run, k, phase, j, ch), __ATOMIC_RELAXED,
+      __hip_atomic_store(gptr(la.q) + base + ch, enc_item(it.run, k, phase, j, ch), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -1333,7 +1333,8 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
     if (threadIdx.x == 0) {
       Item it;
       it.go = 0;
-      const long long T = (long long)atomicAdd(la.ticket, 1ull);
+      const long long T =
+          (long long)__hip_atomic_fetch_add(gptr(la.ticket), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       s_ticket = T;
       if (la.trace && T < total) la.trace[T].t_claim = wall_clock64();
       if (T < total) {
@@ -1342,7 +1343,7 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
           const long long t_begin = wall_clock64();
           unsigned long long v;
           // relaxed polling; the acquire fence follows once the item is known
-          while (!((v = __hip_atomic_load(la.q + T, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 63)) {
+          while (!((v = __hip_atomic_load(gptr(la.q) + T, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 63)) {
             if (ld_relaxed(la.launch_err)) break;
             if (wall_clock64() - t_begin > la.watchdog_ticks) {
               raise_error(la.launch_err, nullptr, ERR_WATCHDOG);
@@ -1431,7 +1432,7 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
         complete_dataflow(la, ra, it);
       } else if (ok) {
         uint32_t* cnt = it.phase == 0 ? ra.cntF : ra.cntA;
-        __hip_atomic_fetch_add(cnt + it.slice, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gptr(cnt) + it.slice, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     __syncthreads();
