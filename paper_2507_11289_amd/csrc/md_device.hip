@@ -125,7 +125,15 @@ constexpr int BCELLS = 9 * BLAYERS;     // staged cells
 constexpr int CAPB = 27 * CELL_CAP;     // staged atoms at most (one full neighbourhood)
 constexpr int QPAD = 16;                // far sentinels after the staged atoms (FP32)
 constexpr float FAR_Q = 1e15f;          // sentinel coordinate: far from everything, |q|^2 finite
-constexpr int FAR_SLOT = CAPB + QPAD - 1;  // always a far sentinel (FP32): the stand-in pair
+
+// FP32 far sentinel entry, built where it is stored: a copy kept across the block loop
+// does not fit the register budget and was spilled to scratch memory, costing a reload
+// and a wait for all outstanding memory operations in every staging
+__device__ __forceinline__ float4 far_entry() {
+  float c = FAR_Q, n = 3.0f * FAR_Q * FAR_Q;
+  asm volatile("" : "+v"(c), "+v"(n));
+  return make_float4(c, c, c, n);
+}
 
 struct BlockHdr {
   int nb_cell[BCELLS];     // global cell of staged cell m
@@ -407,8 +415,7 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
     // list finds no partner in range
     if (lane < QPAD) {
       if constexpr (PREC == 1) {
-        L.q[stot + lane] = make_float4(FAR_Q, FAR_Q, FAR_Q, 3.0f * FAR_Q * FAR_Q);
-        if (lane == 0) L.q[FAR_SLOT] = make_float4(FAR_Q, FAR_Q, FAR_Q, 3.0f * FAR_Q * FAR_Q);
+        L.q[stot + lane] = far_entry();
       } else {
         L.x[stot + lane] = L.y[stot + lane] = L.z[stot + lane] = (double)FAR_Q;
         L.qn[stot + lane] = 3.0f * FAR_Q * FAR_Q;
@@ -492,10 +499,12 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
   const int ntile = __builtin_amdgcn_readfirstlane((o.total + 15) >> 4);
   const unsigned lo_bits = __float_as_uint(g.rc2_lo_f), hi_bits = __float_as_uint(g.rc2_hi_f);
   const float* Lf = reinterpret_cast<const float*>(L.q);
+  const char* Lb = reinterpret_cast<const char*>(L.q);
   for (int u = 0; 16 * u < n_i; u++) {
     const int a = 16 * u + col;
     const bool real = a < n_i;
     const float4 qa = real ? L.q[si + a] : make_float4(FAR_Q, FAR_Q, FAR_Q, 0.0f);
+    const unsigned selfb = 16u * (unsigned)(si + a);  // own entry (only real atoms have marks)
     const float comp = quarter == 0 ? qa.x : (quarter == 1 ? qa.y : qa.z);
     // a missing atom's column is zero and its accumulator huge: never marked
     const float bop = real ? (quarter == 3 ? 1.0f : -2.0f * comp) : 0.0f;
@@ -536,18 +545,18 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
       // candidate 16 t + quarter + 4 r = 4 b + quarter of the batch
       m = __builtin_bitreverse32(m);
       if (tb < 8 * GMASKS) L.gmask[w][tb >> 3][lane] = m;
-      const int fb = beg + 16 * tb + quarter;
       // the marked pairs two at a time, in a fixed order (lowest bit first); a missing
-      // second pair is a far sentinel (out of range and outside the band: it adds
-      // exactly nothing)
+      // second pair is the lane's own atom (r2 = 0: neither in range nor in the band, so
+      // it adds exactly nothing).  Byte offsets into the staged list.
+      const unsigned fbb = 16u * (unsigned)(beg + 16 * tb + quarter);
       while (m) {
-        const int b1 = __ffs(m) - 1;
+        const unsigned b1 = (unsigned)__ffs(m) - 1u;
         m &= m - 1u;
         const bool two = m != 0u;
-        const int b2 = __ffs(m) - 1;
+        const unsigned b2 = (unsigned)__ffs(m) - 1u;
         m &= m - 1u;
-        const float4 q1 = L.q[fb + 4 * b1];
-        const float4 q2 = L.q[two ? fb + 4 * b2 : FAR_SLOT];
+        const float4 q1 = *reinterpret_cast<const float4*>(Lb + fbb + 64u * b1);
+        const float4 q2 = *reinterpret_cast<const float4*>(Lb + (two ? fbb + 64u * b2 : selfb));
         const unsigned t1 = pair32_in<ENERGY, COUNT>(qa, q1, lo_bits, g.uc_f, A);
         const unsigned t2 = pair32_in<ENERGY, COUNT>(qa, q2, lo_bits, g.uc_f, A);
         bmin = min(bmin, min(t1, t2));
