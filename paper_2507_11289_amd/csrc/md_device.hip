@@ -68,26 +68,34 @@ __device__ __forceinline__ void raise_error(uint32_t* err, uint32_t* abort_flag,
 }
 
 // Cell coordinate along one axis: floor(x * (1/l)) with one IEEE multiply, clamped
-// to [0, G-1] (a coordinate equal to L after wrapping belongs to the last cell).
+// to [0, G-1] (a coordinate equal to L after wrapping belongs to the last cell; NaN
+// gives 0).  Branch-free.
 __device__ __forceinline__ int coord_cell(double x, double inv_l, int G) {
-  double f = floor(__dmul_rn(x, inv_l));
-  if (!(f >= 0.0)) return 0;
-  if (f > (double)(G - 1)) return G - 1;
-  return (int)f;
+  const double f = floor(__dmul_rn(x, inv_l));
+  return (int)fmin(fmax(f, 0.0), (double)(G - 1));
+}
+
+// n / d for 0 <= n < 2^51 from inv = 1/d rounded to FP64: the quotient (n + 1/2) / d lies
+// at least 1/(2d) from an integer, and its FP64 product with inv is within
+// (n + 1/2) 2^-52 / d < 1/(2d) of it, so truncation gives the integer quotient (a few
+// FP64 operations instead of an integer division sequence).
+__device__ __forceinline__ int qdiv(int n, double inv) {
+  return (int)__dmul_rn(__dadd_rn((double)n, 0.5), inv);
 }
 
 __device__ __forceinline__ int global_cell(const DGeom& g, int gx, int gy, int gz) {
-  int s = gx / g.ncx;
+  const int s = qdiv(gx, g.inv_ncx);
   return s * g.cps + ((gx - s * g.ncx) * g.G[1] + gy) * g.G[2] + gz;
 }
 
 __device__ __forceinline__ void cell_xyz(const DGeom& g, int c, int& gx, int& gy, int& gz) {
-  int s = c / g.cps;
-  int local = c - s * g.cps;
-  gz = local % g.G[2];
-  int t = local / g.G[2];
-  gy = t % g.G[1];
-  gx = s * g.ncx + t / g.G[1];
+  const int s = qdiv(c, g.inv_cps);
+  const int local = c - s * g.cps;
+  const int t = qdiv(local, g.inv_G[2]);
+  gz = local - t * g.G[2];
+  const int u = qdiv(t, g.inv_G[1]);
+  gy = t - u * g.G[1];
+  gx = s * g.ncx + u;
 }
 
 // Minimum image of one component (the box is at least 3 cells, so the image within
@@ -100,8 +108,10 @@ __device__ __forceinline__ double r2_exact(double dx, double dy, double dz) {
   return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
 }
 
+// Branch-free: both candidates are formed and one is selected.
 __device__ __forceinline__ double wrap1(double x, double L) {
-  return x >= L ? __dsub_rn(x, L) : (x < 0.0 ? __dadd_rn(x, L) : x);
+  const double below = __dsub_rn(x, L), above = __dadd_rn(x, L);
+  return x >= L ? below : (x < 0.0 ? above : x);
 }
 
 // 1/x in FP64 from the hardware reciprocal and two Newton steps (within one ulp).
@@ -771,10 +781,11 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
   const int w = threadIdx.x >> 6;
   // blocks stay within the column and within one aligned group of BZ cells
   auto issue = [&](int xs, StageRegs& R) {
-    const int gz = xs % g.G[2];
-    const int t = xs / g.G[2];
-    const int gy = t % g.G[1];
-    const int gx = slice * g.ncx + t / g.G[1];
+    const int t = qdiv(xs, g.inv_G[2]);
+    const int gz = xs - t * g.G[2];
+    const int u = qdiv(t, g.inv_G[1]);
+    const int gy = t - u * g.G[1];
+    const int gx = slice * g.ncx + u;
     const int nb_max = min(min(BZ - gz % BZ, e - xs), g.G[2] - gz);
     stage_issue(g, ncnt, gx, gy, gz, nb_max, R);
   };
@@ -801,6 +812,13 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
     }
     __syncthreads();  // every wave is done with the previous block's LDS
     const int nb = stage_commit<PREC>(g, cells, R, L);
+    if (OWN) {
+      // the barriers have waited for the own cell's loads; from here on its values count
+      // as plain registers, so the tail does not wait for the next block's count loads
+      // (issued just before it) on their account
+      asm volatile("" : "+v"(o.id), "+v"(o.x[0]), "+v"(o.x[1]), "+v"(o.x[2]), "+v"(o.v[0]), "+v"(o.v[1]),
+                   "+v"(o.v[2]));
+    }
     block_force<PREC, ENERGY, COUNT>(g, cells, L, o);
     x += nb;
     const bool more = x < e;
@@ -838,7 +856,7 @@ __device__ __forceinline__ void acc_zero(ItemAcc& a) {
 // SCALE: the thermostat factor lam multiplies v(t) first (the forces come from the
 // thermostat's force pass; energies were sampled there).
 template <bool ENERGY, bool COUNT, bool SCALE>
-__device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first, ItemAcc& acc,
+__device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old, int first, ItemAcc& acc,
                         uint32_t* abort_flag, double lam) {
   const DGeom& g = ra.g;
   const int lane = __lane_id();
@@ -850,7 +868,6 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first
     return;
   }
   const bool own = lane < o.n;
-  const int s_old = c / g.cps;
   double xn[3] = {0, 0, 0}, vh[3] = {0, 0, 0};
   uint32_t id = 0;
   int dest = c;
@@ -886,9 +903,10 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int first
       gc[d] = coord_cell(xn[d], g.inv_l[d], g.G[d]);
     }
     id = o.id;
-    dest = global_cell(g, gc[0], gc[1], gc[2]);
-    const int s_new = gc[0] / g.ncx;
-    const int delta = (s_new - s_old + g.S) % g.S;
+    const int s_new = qdiv(gc[0], g.inv_ncx);
+    dest = s_new * g.cps + ((gc[0] - s_new * g.ncx) * g.G[1] + gc[1]) * g.G[2] + gc[2];
+    int delta = s_new - s_old;  // both in [0, S): (s_new - s_old) mod S
+    if (delta < 0) delta += g.S;
     if (delta == 1) dir = 2;
     else if (delta == g.S - 1) dir = 1;
     else if (delta != 0) bad |= ERR_DISPLACEMENT;
@@ -1087,7 +1105,7 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L
   acc_zero(acc);
   for_blocks<PREC, ENERGY, COUNT, true>(ra.g, ra.cells[src], ra.ncnt[src], it.slice, b, e, L, [&](const ForceOut& o) {
     if (NVT) p2_force_tail<ENERGY, COUNT>(ra, o, src, first, acc);
-    else p2_tail<ENERGY, COUNT, false>(ra, o, src, first, acc, abort_flag, 1.0);
+    else p2_tail<ENERGY, COUNT, false>(ra, o, src, it.slice, first, acc, abort_flag, 1.0);
   });
   // wave reductions (fixed butterfly), then waves in order
   double u = acc.u, w = acc.w, k = acc.k, kt = acc.kt;
@@ -1215,7 +1233,7 @@ __device__ void run_p2b_item(const RunArgs& ra, const Item& it, double* s_lam, u
       }
       o.id = cids(ib)[lane];
     }
-    p2_tail<false, false, true>(ra, o, src, first, acc, abort_flag, lam);
+    p2_tail<false, false, true>(ra, o, src, it.slice, first, acc, abort_flag, lam);
   }
   if (lane == 0) {
     s_cnt[wave][0] = acc.left;

@@ -108,7 +108,10 @@ static int make_geom(const double box[3], int slices, double rc, double dt, int 
     g->halfL[d] = 0.5 * box[d];
     g->l[d] = box[d] / (double)g->G[d];
     g->inv_l[d] = 1.0 / g->l[d];
+    g->inv_G[d] = 1.0 / (double)g->G[d];
   }
+  g->inv_ncx = 1.0 / (double)g->ncx;
+  g->inv_cps = 1.0 / (double)cps;
   g->rc2 = rc * rc;
   const double ir2 = 1.0 / g->rc2;
   const double ir6 = ir2 * ir2 * ir2;

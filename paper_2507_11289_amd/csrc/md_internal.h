@@ -33,6 +33,8 @@ struct DGeom {
   double halfL[3];
   double l[3];
   double inv_l[3];
+  double inv_ncx, inv_cps, inv_G[3];  // 1/ncx, 1/cps, 1/G rounded to FP64: exact quotients
+                                      // of non-negative ints (see qdiv)
   double rc2;      // rc^2
   double uc;       // pair energy at rc (subtracted from every pair energy)
   double dt, hdt;  // step and half step
