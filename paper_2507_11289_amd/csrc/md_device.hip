@@ -450,6 +450,7 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
       const int k = f - __shfl(pre, m & 63);
       const int cm = __shfl(R.nc, m & 63);
       mm[r] = m;
+      x[r] = y[r] = z[r] = 0.0;
       if (f < stot) {
         const gdouble* jb = cblk(cells, cm);
         x[r] = jb[k];
@@ -462,6 +463,11 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
       const int f = base + tid + WG * r;
       if (f < stot) stage_put<PREC>(g, R, L, mm[r], f, x[r], y[r], z[r], wrap);
     }
+    // every round's registers are read on every path: otherwise a load whose value is
+    // (in the compiler's view) left unread looks outstanding at the next pass, and each
+    // round then waits for the loads of the round before it
+#pragma unroll
+    for (int r = 0; r < SROUNDS; r++) asm volatile("" ::"v"(x[r]), "v"(y[r]), "v"(z[r]));
   }
   __syncthreads();
   return nb;
