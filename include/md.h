@@ -66,7 +66,7 @@ enum md_option {
                                    bitwise identical for every order */
     MD_OPT_ORDER_SEED = 3,      /* seed of MD_ORDER_RANDOM */
     MD_OPT_MIGRATION_LOG = 4,   /* 1: record per-step, per-slice migration counts */
-    MD_OPT_CHUNK_CELLS = 5,     /* cells per work item (0 = automatic: about 2600 atoms per item
+    MD_OPT_CHUNK_CELLS = 5,     /* cells per work item (0 = automatic: about 2200 atoms per item
                                    in FP32-force mode, 1900 in FP64, at least 32 cells) */
     MD_OPT_COUNT_PAIRS = 6,     /* 1: count candidates and in-range partners (slower) */
     MD_OPT_WATCHDOG_MS = 7,     /* device wait budget in ms (default 20000) */

@@ -414,7 +414,7 @@ static int auto_chunks(const DGeom& g, int64_t chunk_cells, int64_t n_atoms) {
   if (chunk_cells > 0) {
     nch = (g.cps + chunk_cells - 1) / chunk_cells;
   } else {
-    const double atoms_per_item = g.prec == 1 ? 2600.0 : 1900.0;
+    const double atoms_per_item = g.prec == 1 ? 2200.0 : 1900.0;
     nch = std::llround((double)n_atoms / ((double)g.S * atoms_per_item));
     nch = std::min<int64_t>(nch, (g.cps + 31) / 32);
   }
