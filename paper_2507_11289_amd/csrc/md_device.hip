@@ -498,8 +498,8 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 //     FP32 arithmetic and range decision of a pair-by-pair loop; a running minimum of
 //     rb - lo_bits tells whether any pair fell in the guard band, and those pairs are
 //     then decided in FP64 (revisiting the lane's marked candidates from saved masks).
-// An atom's four quarter partials are added in quarter order, so every sum has a fixed
-// order.  Wave-level (no barrier).
+// An atom's four quarter partials are added as (q0 + q1) + (q2 + q3), so every sum has a
+// fixed order.  Wave-level (no barrier).
 template <bool ENERGY, bool COUNT>
 __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockLDS<1>& L, int w,
                               ForceOut& o) {
@@ -622,10 +622,14 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
           }
       }
     }
-    // quarter partials of column col, added in quarter order; lane 16 u + col keeps them
-    const float sx = ((__shfl(A.fx, col) + __shfl(A.fx, col + 16)) + __shfl(A.fx, col + 32)) + __shfl(A.fx, col + 48);
-    const float sy = ((__shfl(A.fy, col) + __shfl(A.fy, col + 16)) + __shfl(A.fy, col + 32)) + __shfl(A.fy, col + 48);
-    const float sz = ((__shfl(A.fz, col) + __shfl(A.fz, col + 16)) + __shfl(A.fz, col + 32)) + __shfl(A.fz, col + 48);
+    // quarter partials of column col as (q0 + q1) + (q2 + q3), by two exchanges; IEEE
+    // addition is commutative, so all four lanes of the column hold the same sum and lane
+    // 16 u + col keeps it
+    auto qsum = [](float v) {
+      v += __shfl_xor(v, 16);
+      return v + __shfl_xor(v, 32);
+    };
+    const float sx = qsum(A.fx), sy = qsum(A.fy), sz = qsum(A.fz);
     const bool keep = quarter == u && real;
     if (keep) {
       o.fx = sx;
@@ -633,10 +637,14 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
       o.fz = sz;
     }
     if constexpr (ENERGY || COUNT) {
-      // energy, virial and partner count (sampled steps, count mode): FP64, quarter order
-      const double su = ((__shfl(A.u, col) + __shfl(A.u, col + 16)) + __shfl(A.u, col + 32)) + __shfl(A.u, col + 48);
-      const double sw = ((__shfl(A.w, col) + __shfl(A.w, col + 16)) + __shfl(A.w, col + 32)) + __shfl(A.w, col + 48);
-      const unsigned sp = __shfl(A.pc, col) + __shfl(A.pc, col + 16) + __shfl(A.pc, col + 32) + __shfl(A.pc, col + 48);
+      // energy, virial and partner count (sampled steps, count mode): FP64, same order
+      auto qsum64 = [](double v) {
+        v += __shfl_xor(v, 16);
+        return v + __shfl_xor(v, 32);
+      };
+      const double su = qsum64(A.u), sw = qsum64(A.w);
+      unsigned sp = A.pc + __shfl_xor(A.pc, 16);
+      sp += __shfl_xor(sp, 32);
       if (keep) {
         o.uh = 0.5 * su;
         o.wh = 0.5 * sw;
@@ -904,8 +912,9 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old
       vh[d] = __dadd_rn(vf[d], __dmul_rn(g.hdt, F[d]));
       const double x = __dadd_rn(o.x[d], __dmul_rn(g.dt, vh[d]));
       xn[d] = wrap1(x, g.L[d]);
-      if (!isfinite(xn[d]) || !isfinite(vh[d]) || !(xn[d] >= 0.0) || xn[d] > g.L[d])
-        bad |= ERR_NONFINITE;
+      // NaN and infinite positions fail one of the two tests, and a non-finite velocity
+      // always gives a non-finite position (dt is finite and positive)
+      if (!(xn[d] >= 0.0) || xn[d] > g.L[d]) bad |= ERR_NONFINITE;
       gc[d] = coord_cell(xn[d], g.inv_l[d], g.G[d]);
     }
     id = o.id;
