@@ -160,7 +160,8 @@ constexpr int GMASKS = 4;  // pre-filter masks kept per lane for the guard-band 
 template <> struct BlockLDS<1> {  // FP32: positions relative to the block origin, |q|^2
   BlockHdr h;
   float4 q[CAPB + QPAD];
-  unsigned gmask[WAVES][GMASKS][64];  // each wave's pass-1 marks of its current atom batch
+  unsigned gmask[WAVES][GMASKS + 1][64];  // each wave's pass-1 marks of its current atom batch
+                                         // (and a padding word read ahead, never used)
 };
 template <> struct BlockLDS<0> {  // FP64: raw positions, plus per entry the periodic image
   BlockHdr h;                     // and the FP32 |q|^2 of the matrix-core pre-filter
@@ -543,39 +544,63 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
       m = __builtin_amdgcn_alignbit(m, __float_as_uint(d[2]), 31);
       return __builtin_amdgcn_alignbit(m, __float_as_uint(d[3]), 31);
     };
-    for (int tb = 0; tb < ntile; tb += 8) {
-      const int cn = min(8, ntile - tb);
-      unsigned m = 0u;
-      if (cn == 8) {
-        // a full batch: all operand reads first, then the matrix ops
-        float av[8];
+    for (int tg = 0; tg < ntile; tg += 8 * GMASKS) {
+      // groups of up to GMASKS batches of 8 tiles; pass 1 keeps one mask word per batch
+      // in LDS (the guard pass below reads them again)
+      const int nw = min(GMASKS, (ntile - tg + 7) >> 3);
+      for (int bi = 0; bi < nw; bi++) {
+        const int tb = tg + 8 * bi;
+        const int cn = min(8, ntile - tb);
+        unsigned m = 0u;
+        if (cn == 8) {
+          // a full batch: all operand reads first, then the matrix ops
+          float av[8];
 #pragma unroll
-        for (int t = 0; t < 8; t++) av[t] = ap[64 * (tb + t)];
+          for (int t = 0; t < 8; t++) av[t] = ap[64 * (tb + t)];
 #pragma unroll
-        for (int t = 0; t < 8; t++) m = mark(m, av[t]);
-      } else {
-        for (int t = 0; t < cn; t++) m = mark(m, ap[64 * (tb + t)]);
-        m <<= 32 - 4 * cn;
+          for (int t = 0; t < 8; t++) m = mark(m, av[t]);
+        } else {
+          for (int t = 0; t < cn; t++) m = mark(m, ap[64 * (tb + t)]);
+          m <<= 32 - 4 * cn;
+        }
+        // after the reversal, bit b = 4 t + r marks row 4 quarter + r of tile t, i.e.
+        // candidate 16 t + quarter + 4 r = 4 b + quarter of the batch
+        L.gmask[w][bi][lane] = __builtin_bitreverse32(m);
       }
-      // after the reversal, bit b = 4 t + r marks row 4 quarter + r of tile t, i.e.
-      // candidate 16 t + quarter + 4 r = 4 b + quarter of the batch
-      m = __builtin_bitreverse32(m);
-      if (tb < 8 * GMASKS) L.gmask[w][tb >> 3][lane] = m;
-      // the marked pairs two at a time, in a fixed order (lowest bit first); a missing
-      // second pair is the lane's own atom (r2 = 0: neither in range nor in the band, so
-      // it adds exactly nothing).  Byte offsets into the staged list.
-      const unsigned fbb = 16u * (unsigned)(beg + 16 * tb + quarter);
-      while (m) {
+      // Pass 2: every lane walks its own words in order, the marked pairs two at a time
+      // and lowest bit first (a fixed order), moving to its next word as soon as one is
+      // used up; lanes do not wait for each other at word ends, so the wave runs for the
+      // largest per-lane total rather than the sum of per-batch maxima.  A missing pair
+      // is the lane's own atom (r2 = 0: neither in range nor in the band, so it adds
+      // exactly nothing).  Byte offsets into the staged list.
+      const unsigned fb0 = 16u * (unsigned)(beg + 16 * tg + quarter);
+      const unsigned* gm = &L.gmask[w][0][lane];  // word j of the lane at gm[64 j]
+      const int last = nw - 1;
+      unsigned m = gm[0];
+      unsigned nx = gm[64];  // the word after m (a padding word follows the last one)
+      int k = 0;             // word of m
+      while (m != 0u || k < last) {
+        if (m == 0u) {
+          m = nx;
+          k++;
+        }
+        nx = gm[64 * (k + 1)];
+        const unsigned fbb = fb0 + 2048u * (unsigned)k;
+        const bool one = m != 0u;
         const unsigned b1 = (unsigned)__ffs(m) - 1u;
         m &= m - 1u;
         const bool two = m != 0u;
         const unsigned b2 = (unsigned)__ffs(m) - 1u;
         m &= m - 1u;
-        const float4 q1 = *reinterpret_cast<const float4*>(Lb + fbb + 64u * b1);
+        const float4 q1 = *reinterpret_cast<const float4*>(Lb + (one ? fbb + 64u * b1 : selfb));
         const float4 q2 = *reinterpret_cast<const float4*>(Lb + (two ? fbb + 64u * b2 : selfb));
         const unsigned t1 = pair32_in<ENERGY, COUNT>(qa, q1, lo_bits, g.uc_f, A);
         const unsigned t2 = pair32_in<ENERGY, COUNT>(qa, q2, lo_bits, g.uc_f, A);
         bmin = min(bmin, min(t1, t2));
+        // the read-ahead word is needed by the end of this iteration: its LDS read stays
+        // at the top (not moved down to the next iteration's refill, which would expose
+        // its latency every iteration)
+        asm volatile("" ::"v"(nx));
       }
     }
     // guard band: decide those pairs in FP64 exactly as the FP64 path would.  Every pair
