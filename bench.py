@@ -36,14 +36,14 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11289_amd", "csrc", f) for f in
 # counters on a plain device copy of known size (profiles/persistent_f32_lean_lj_fluid_4m.md).
 # Valid only for the kernel and host sources they were taken on (sha256 below); otherwise null.
 TRAFFIC = {
-    "source_sha256": "b4d9215efd975fe86f373b4c9fe2870d3af57dcc81f7a78738756f118e936bcf",
+    "source_sha256": "87b65f99fbb59e66b0da7cc13052ba23a2b05c0b24dc9adc5a565e1219f70fdd",
     "workload": "lj_fluid_4m",
     "steps_per_launch": 100,
-    "fetch_kib_per_launch": 69114304,      # FETCH_SIZE, mean of 3 dispatches
-    "write_kib_per_launch": 26319854,      # WRITE_SIZE, mean of 3 dispatches
+    "fetch_kib_per_launch": 68462069,      # FETCH_SIZE, mean of 3 dispatches
+    "write_kib_per_launch": 26017700,      # WRITE_SIZE, mean of 3 dispatches
     "copy_fetch_factor": 0.50001,          # FETCH_SIZE KiB / KiB really read by a 1 GiB copy
     "copy_write_factor": 1.00000,          # WRITE_SIZE KiB / KiB really written by it
-    "hbm_bytes_per_launch": 1.6849e+11,
+    "hbm_bytes_per_launch": 1.6685e+11,
 }
 
 
