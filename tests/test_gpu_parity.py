@@ -136,6 +136,41 @@ def test_brute_force_tiny_systems():
                 assert st.candidates == int(c["cand"].sum())
 
 
+def test_dense_cells_many_batches_and_mask_groups():
+    """Jittered lattices at rho = 3 (about 48 atoms per cell, up to 62; nearest
+    neighbours about 0.8 apart): several 16-atom batches per cell, windows of 80 and more
+    16-candidate tiles (more than one group of pre-filter mask words in the FP32 pair
+    walk), staged blocks cut below 4 cells by the staging capacity, and periodic images
+    on every side.  Forces, energy and pair counts against the oracle."""
+    for n, aspect, slices in [(1300, (1, 1, 1), 3), (2600, (2, 1, 1), 3)]:
+        box, pos, vel, _ = inputs.homogeneous(n, 3.0, 1.0, 17, aspect=aspect)
+        g = ref.geometry(box, slices, 2.5)
+        cnt = np.bincount(ref.bin_atoms(g, pos)[2])
+        assert cnt.max() <= 64 and cnt.mean() > 40  # the case this test is for
+        o = ref.forces_cells(g, pos)
+        oU, oK, oW = ref.energy(g, pos, vel)
+        assert (o["cand"].max() + 15) // 16 > 64  # windows beyond two mask groups
+        for prec in PRECS:
+            say(f"[gpu] dense cells n={n} aspect={aspect} slices={slices} precision={prec}")
+            # a tiny step: the counting step then moves no atom into a full cell
+            with md.Sim(box, slices, 2.5, 1e-5, prec) as sim:
+                sim.set_option(md.OPT_COUNT_PAIRS, 1)
+                sim.load(pos, vel)
+                np.testing.assert_array_equal(sim.cells(), ref.bin_atoms(g, pos)[2])
+                _, _, F = sim.state()
+                e = ref.force_error(F, o["F"], o["scale"])
+                say(f"    max e_i = {e.max():.3e}")
+                assert e.max() <= TOL[prec]
+                U, K, W = sim.energy_virial()
+                rel = 1e-12 if prec == md.MD_FP64 else 1e-6
+                assert U == pytest.approx(oU, rel=rel)
+                assert W == pytest.approx(oW, rel=rel)
+                sim.step(1)
+                st = sim.stats()
+                assert st.candidates == int(o["cand"].sum())
+                assert st.in_range == int(o["inr"].sum())
+
+
 def cutoff_pairs(seed=11):
     """Isolated atom pairs at separations rc (1 + delta), delta from -2^-12 to +2^-12:
     some pairs lie inside the FP32 guard band |r2 - rc^2| <= 2^-16 rc^2 (decided again in
