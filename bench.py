@@ -36,14 +36,14 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11289_amd", "csrc", f) for f in
 # counters on a plain device copy of known size (profiles/persistent_f32_lean_lj_fluid_4m.md).
 # Valid only for the kernel and host sources they were taken on (sha256 below); otherwise null.
 TRAFFIC = {
-    "source_sha256": "87b65f99fbb59e66b0da7cc13052ba23a2b05c0b24dc9adc5a565e1219f70fdd",
+    "source_sha256": "e7c4eafbca2018a9c9ac180a1c470ab265840b6a03b37b987dd873dbac06d807",
     "workload": "lj_fluid_4m",
     "steps_per_launch": 100,
-    "fetch_kib_per_launch": 68462069,      # FETCH_SIZE, mean of 3 dispatches
-    "write_kib_per_launch": 26017700,      # WRITE_SIZE, mean of 3 dispatches
+    "fetch_kib_per_launch": 68517034,      # FETCH_SIZE, mean of 3 dispatches
+    "write_kib_per_launch": 26019627,      # WRITE_SIZE, mean of 3 dispatches
     "copy_fetch_factor": 0.50001,          # FETCH_SIZE KiB / KiB really read by a 1 GiB copy
     "copy_write_factor": 1.00000,          # WRITE_SIZE KiB / KiB really written by it
-    "hbm_bytes_per_launch": 1.6685e+11,
+    "hbm_bytes_per_launch": 1.6696e+11,
 }
 
 

@@ -156,7 +156,8 @@ struct BlockHdr {
 };
 
 template <int PREC> struct BlockLDS;
-constexpr int GMASKS = 4;  // pre-filter masks kept per lane for the guard-band pass (32 tiles)
+constexpr int GMASKS = 4;  // pre-filter mask words kept per lane: one group of the pair walk and the
+                           // guard-band pass (32 tiles)
 template <> struct BlockLDS<1> {  // FP32: positions relative to the block origin, |q|^2
   BlockHdr h;
   float4 q[CAPB + QPAD];
@@ -440,6 +441,10 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
   for (int base = 0; base < stot; base += WG * SROUNDS) {
     int mm[SROUNDS];
     double x[SROUNDS], y[SROUNDS], z[SROUNDS];
+    // raised wave priority while the list loads are found and issued: the SIMD's other
+    // waves are mostly in VALU-heavy pair loops, and an early issue lets the memory round
+    // trip overlap their work
+    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int r = 0; r < SROUNDS; r++) {
       const int f = base + tid + WG * r;
@@ -459,6 +464,7 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
         z[r] = jb[2 * CELL_CAP + k];
       }
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int r = 0; r < SROUNDS; r++) {
       const int f = base + tid + WG * r;
