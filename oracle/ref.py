@@ -212,5 +212,8 @@ def force_error(F_test, F_ref, scale):
     e = np.zeros_like(d)
     nz = scale > 0
     e[nz] = d[nz] / scale[nz]
-    e[~nz] = np.where(d[~nz] == 0.0, 0.0, np.inf)
+    # no partner: the force must be exactly zero (compared component by component: the
+    # norm of a tiny difference can underflow to 0)
+    exact = (F_test[~nz] == F_ref[~nz]).all(axis=1)
+    e[~nz] = np.where(exact, 0.0, np.inf)
     return e
