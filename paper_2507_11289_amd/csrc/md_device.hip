@@ -58,6 +58,24 @@ __device__ __forceinline__ const guint32* cids(const gdouble* b) {
   return (const guint32*)(b + CELL_DOUBLES);
 }
 
+// FP64 sums, differences and products rounded one operation at a time, in the order
+// written, as the oracle computes them.  They are never fused into multiply-adds: this
+// toolchain's __dadd_rn / __dmul_rn are plain operators, and the default contraction
+// mode fuses a product feeding a sum into one FMA (one rounding instead of two), which
+// would move r^2 off the oracle's value and could flip a cutoff decision.
+__device__ __forceinline__ double add_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+__device__ __forceinline__ double sub_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a - b;
+}
+__device__ __forceinline__ double mul_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
 __device__ __forceinline__ unsigned ld_relaxed(const uint32_t* p) {
   return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -71,7 +89,7 @@ __device__ __forceinline__ void raise_error(uint32_t* err, uint32_t* abort_flag,
 // to [0, G-1] (a coordinate equal to L after wrapping belongs to the last cell; NaN
 // gives 0).  Branch-free.
 __device__ __forceinline__ int coord_cell(double x, double inv_l, int G) {
-  const double f = floor(__dmul_rn(x, inv_l));
+  const double f = floor(mul_rn(x, inv_l));
   return (int)fmin(fmax(f, 0.0), (double)(G - 1));
 }
 
@@ -80,7 +98,7 @@ __device__ __forceinline__ int coord_cell(double x, double inv_l, int G) {
 // (n + 1/2) 2^-52 / d < 1/(2d) of it, so truncation gives the integer quotient (a few
 // FP64 operations instead of an integer division sequence).
 __device__ __forceinline__ int qdiv(int n, double inv) {
-  return (int)__dmul_rn(__dadd_rn((double)n, 0.5), inv);
+  return (int)mul_rn(add_rn((double)n, 0.5), inv);
 }
 
 __device__ __forceinline__ int global_cell(const DGeom& g, int gx, int gy, int gz) {
@@ -101,16 +119,16 @@ __device__ __forceinline__ void cell_xyz(const DGeom& g, int c, int& gx, int& gy
 // Minimum image of one component (the box is at least 3 cells, so the image within
 // rc is unique).
 __device__ __forceinline__ double min_img(double d, double L, double h) {
-  return d > h ? __dsub_rn(d, L) : (d < -h ? __dadd_rn(d, L) : d);
+  return d > h ? sub_rn(d, L) : (d < -h ? add_rn(d, L) : d);
 }
 
 __device__ __forceinline__ double r2_exact(double dx, double dy, double dz) {
-  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  return add_rn(add_rn(mul_rn(dx, dx), mul_rn(dy, dy)), mul_rn(dz, dz));
 }
 
 // Branch-free: both candidates are formed and one is selected.
 __device__ __forceinline__ double wrap1(double x, double L) {
-  const double below = __dsub_rn(x, L), above = __dadd_rn(x, L);
+  const double below = sub_rn(x, L), above = add_rn(x, L);
   return x >= L ? below : (x < 0.0 ? above : x);
 }
 
@@ -251,7 +269,7 @@ __device__ __forceinline__ void pair32_add(float dx, float dy, float dz, float r
 template <bool ENERGY, bool COUNT, bool WRAP>
 __device__ __forceinline__ void pair64(const DGeom& g, double xi, double yi, double zi, double xj, double yj,
                                        double zj, Acc<double>& a) {
-  double dx = __dsub_rn(xi, xj), dy = __dsub_rn(yi, yj), dz = __dsub_rn(zi, zj);
+  double dx = sub_rn(xi, xj), dy = sub_rn(yi, yj), dz = sub_rn(zi, zj);
   if (WRAP) {
     dx = min_img(dx, g.L[0], g.halfL[0]);
     dy = min_img(dy, g.L[1], g.halfL[1]);
@@ -333,14 +351,14 @@ __device__ __forceinline__ void stage_issue(const DGeom& g, const uint32_t* ncnt
 // cells, so a pair's FP32 arithmetic depends on the cell only, not on how cells form
 // blocks.
 __device__ __forceinline__ void block_origin(const DGeom& g, int gx, int gy, int z0, double o[3]) {
-  o[0] = __dmul_rn((double)gx, g.l[0]);
-  o[1] = __dmul_rn((double)gy, g.l[1]);
-  o[2] = __dmul_rn((double)(z0 - z0 % BZ), g.l[2]);
+  o[0] = mul_rn((double)gx, g.l[0]);
+  o[1] = mul_rn((double)gy, g.l[1]);
+  o[2] = mul_rn((double)(z0 - z0 % BZ), g.l[2]);
 }
 
 // FP32 coordinate of a staged position: (x + s L) - o, rounded once to FP32.
 __device__ __forceinline__ float rel32(double x, int s, double L, double o) {
-  return (float)__dsub_rn(__dadd_rn(x, (double)s * L), o);
+  return (float)sub_rn(add_rn(x, (double)s * L), o);
 }
 
 // wrap: some staged cell of the block is a periodic image (its coordinates are shifted
@@ -353,18 +371,18 @@ __device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, Bl
   if constexpr (PREC == 1) {
     float qx, qy, qz;
     if (!wrap) {
-      qx = (float)__dsub_rn(x, o[0]);
-      qy = (float)__dsub_rn(y, o[1]);
-      qz = (float)__dsub_rn(z, o[2]);
+      qx = (float)sub_rn(x, o[0]);
+      qy = (float)sub_rn(y, o[1]);
+      qz = (float)sub_rn(z, o[2]);
     } else {
       int nx, ny, nz;
       staged_cell_xyz(R.gx, R.gy, R.z0, m, nx, ny, nz);
       const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
       const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
       const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
-      qx = (float)__dsub_rn(__dadd_rn(x, shx), o[0]);
-      qy = (float)__dsub_rn(__dadd_rn(y, shy), o[1]);
-      qz = (float)__dsub_rn(__dadd_rn(z, shz), o[2]);
+      qx = (float)sub_rn(add_rn(x, shx), o[0]);
+      qy = (float)sub_rn(add_rn(y, shy), o[1]);
+      qz = (float)sub_rn(add_rn(z, shz), o[2]);
     }
     // w: |q|^2, the norm term of the matrix-core distance test
     L.q[p] = make_float4(qx, qy, qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
@@ -629,9 +647,9 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
             if (sm + step < BCELLS && L.h.pre[sm + step] <= f) sm += step;
           const gdouble* jb = cblk(cells, L.h.nb_cell[sm]);
           const int k = f - L.h.pre[sm];
-          const double ex = min_img(__dsub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
-          const double ey = min_img(__dsub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
-          const double ez = min_img(__dsub_rn(zi, jb[2 * CELL_CAP + k]), g.L[2], g.halfL[2]);
+          const double ex = min_img(sub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
+          const double ey = min_img(sub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
+          const double ez = min_img(sub_rn(zi, jb[2 * CELL_CAP + k]), g.L[2], g.halfL[2]);
           if (r2_exact(ex, ey, ez) <= g.rc2) pair32_add<ENERGY, COUNT>(dx, dy, dz, r2, g.uc_f, A);
         }
       };
@@ -924,12 +942,12 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old
 #pragma unroll
     for (int d = 0; d < 3; d++) {
       const double v = o.v[d];
-      vf[d] = first ? v : __dadd_rn(v, __dmul_rn(g.hdt, F[d]));
-      if (SCALE) vf[d] = __dmul_rn(lam, vf[d]);
+      vf[d] = first ? v : add_rn(v, mul_rn(g.hdt, F[d]));
+      if (SCALE) vf[d] = mul_rn(lam, vf[d]);
     }
     if (ENERGY) {
-      acc.k += 0.5 * __dadd_rn(__dadd_rn(__dmul_rn(vf[0], vf[0]), __dmul_rn(vf[1], vf[1])),
-                               __dmul_rn(vf[2], vf[2]));
+      acc.k += 0.5 * add_rn(add_rn(mul_rn(vf[0], vf[0]), mul_rn(vf[1], vf[1])),
+                               mul_rn(vf[2], vf[2]));
       acc.u += o.uh;
       acc.w += o.wh;
     }
@@ -940,8 +958,8 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old
     int gc[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-      vh[d] = __dadd_rn(vf[d], __dmul_rn(g.hdt, F[d]));
-      const double x = __dadd_rn(o.x[d], __dmul_rn(g.dt, vh[d]));
+      vh[d] = add_rn(vf[d], mul_rn(g.hdt, F[d]));
+      const double x = add_rn(o.x[d], mul_rn(g.dt, vh[d]));
       xn[d] = wrap1(x, g.L[d]);
       // NaN and infinite positions fail one of the two tests, and a non-finite velocity
       // always gives a non-finite position (dt is finite and positive)
@@ -1000,10 +1018,10 @@ __device__ void p2_force_tail(const RunArgs& ra, const ForceOut& o, int src, int
 #pragma unroll
   for (int d = 0; d < 3; d++) {
     const double v = o.v[d];
-    vf[d] = first ? v : __dadd_rn(v, __dmul_rn(g.hdt, F[d]));
+    vf[d] = first ? v : add_rn(v, mul_rn(g.hdt, F[d]));
   }
   const double ke =
-      0.5 * __dadd_rn(__dadd_rn(__dmul_rn(vf[0], vf[0]), __dmul_rn(vf[1], vf[1])), __dmul_rn(vf[2], vf[2]));
+      0.5 * add_rn(add_rn(mul_rn(vf[0], vf[0]), mul_rn(vf[1], vf[1])), mul_rn(vf[2], vf[2]));
   acc.kt += ke;
   acc.nt += 1u;
   if (ENERGY) {
@@ -1067,7 +1085,7 @@ __device__ void p1_range(const RunArgs& ra, int b, int e, int dst, int wave, uin
       n_stay = gptr(ra.ncnt[dst])[c];
       n_in = gptr(ra.nin[dst])[c];
       gptr(ra.nin[src])[c] = 0u;
-      if (n_stay + n_in > (unsigned)CELL_CAP) {
+      if (n_stay + n_in > (unsigned)ra.g.cap) {
         raise_error(ra.err, abort_flag, ERR_CAPACITY);
         n_in = 0;
       }
@@ -1248,7 +1266,7 @@ __device__ void run_p2b_item(const RunArgs& ra, const Item& it, double* s_lam, u
       K += kp[2 * ch];
       n += kp[2 * ch + 1];
     }
-    *s_lam = (n > 0.0 && K > 0.0) ? __dsqrt_rn(__ddiv_rn(__dmul_rn(__dmul_rn(3.0, n), ra.thermo_T), __dmul_rn(2.0, K)))
+    *s_lam = (n > 0.0 && K > 0.0) ? __dsqrt_rn(__ddiv_rn(mul_rn(mul_rn(3.0, n), ra.thermo_T), mul_rn(2.0, K)))
                                   : 1.0;
   }
   __syncthreads();
@@ -1578,7 +1596,7 @@ __global__ void load_scatter_kernel(DGeom g, const double* pos, const double* ve
     for (int d = 0; d < 3; d++) gc[d] = coord_cell(pos[3 * i + d], g.inv_l[d], g.G[d]);
     const int c = global_cell(g, gc[0], gc[1], gc[2]);
     const unsigned slot = atomicAdd(ncnt + c, 1u);
-    if (slot < (unsigned)CELL_CAP) {
+    if (slot < (unsigned)g.cap) {
       gdouble* b = cblk(cells, c);
       for (int d = 0; d < 3; d++) {
         b[d * CELL_CAP + slot] = pos[3 * i + d];
@@ -1596,7 +1614,7 @@ __global__ __launch_bounds__(WG) void sort_cells_kernel(DGeom g, unsigned char* 
   const int c = blockIdx.x * WAVES + (threadIdx.x >> 6);
   if (c >= g.ncell) return;
   unsigned n = ncnt[c];
-  if (n > (unsigned)CELL_CAP) {
+  if (n > (unsigned)g.cap) {
     if ((threadIdx.x & 63) == 0) atomicOr(err, ERR_CAPACITY);
     return;
   }
@@ -1631,14 +1649,14 @@ __global__ __launch_bounds__(WG) void sync_kernel(DGeom g, const unsigned char* 
       double vf[3];
       for (int d = 0; d < 3; d++) {
         const double v = ib[(3 + d) * CELL_CAP + lane];
-        vf[d] = first ? v : __dadd_rn(v, __dmul_rn(g.hdt, F[d]));
+        vf[d] = first ? v : add_rn(v, mul_rn(g.hdt, F[d]));
         if (out_pos) out_pos[3 * (size_t)id + d] = ib[d * CELL_CAP + lane];
         if (out_vel) out_vel[3 * (size_t)id + d] = vf[d];
         if (out_force) out_force[3 * (size_t)id + d] = F[d];
         if (!isfinite(F[d]) || !isfinite(vf[d])) atomicOr(err, ERR_NONFINITE);
       }
-      k += 0.5 * __dadd_rn(__dadd_rn(__dmul_rn(vf[0], vf[0]), __dmul_rn(vf[1], vf[1])),
-                           __dmul_rn(vf[2], vf[2]));
+      k += 0.5 * add_rn(add_rn(mul_rn(vf[0], vf[0]), mul_rn(vf[1], vf[1])),
+                           mul_rn(vf[2], vf[2]));
       u += o.uh;
       w += o.wh;
     }

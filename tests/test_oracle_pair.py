@@ -113,3 +113,22 @@ def test_minimum_image_across_the_boundary():
 def test_energy_shift_value(geom):
     assert geom.uc == pytest.approx(float(4 * (RC ** -12 - RC ** -6)), rel=1e-15)
     assert geom.uc == pytest.approx(-0.016316891136, rel=1e-10)
+
+
+def test_cutoff_decision_uses_unfused_r2():
+    """r^2 is (dx dx + dy dy) + dz dz with every operation rounded (no fused multiply-add):
+    on separations whose decision a fused evaluation would flip, the oracle's r^2 is the
+    unfused value bit for bit and its decision follows it."""
+    from tests.cutoff_cases import flip_separations, r2_unfused
+    g = ref.geometry([60.0, 60.0, 60.0], 4, 2.5)
+    seps = flip_separations(24)
+    n_in = 0
+    for d in seps:
+        ri = np.array([30.0, 30.0, 30.0])
+        rj = ri - d
+        assert (ri - rj == d).all()
+        inr, _, _, _, _, r2 = ref.pair(g, ri, rj)
+        assert r2 == r2_unfused(d)
+        assert inr == (r2 <= 6.25)
+        n_in += inr
+    assert 0 < n_in < len(seps)
