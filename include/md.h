@@ -48,7 +48,7 @@ enum md_status {
     MD_ECAPACITY = -5,   /* a cell ran out of slots (atoms too crowded) */
     MD_EUNSTABLE = -6,   /* non-finite value, or an atom crossed more than one slice */
     MD_ENOTFOUND = -7,   /* unknown server ticket */
-    MD_EBUSY = -8,       /* server queue full */
+    MD_EBUSY = -8,       /* server queue full: MD_SERVER_MAX_QUEUED runs wait for admission */
     MD_EWATCHDOG = -9    /* a device-side wait exceeded its time budget */
 };
 
@@ -73,7 +73,10 @@ enum md_option {
     MD_OPT_GRID = 8,            /* persistent workgroups (0 = occupancy x CUs) */
     MD_OPT_FAIL_AT_STEP = 9,    /* debug: raise MD_EUNSTABLE when step k is reached (-1 = off) */
     MD_OPT_MAX_STEPS_PER_LAUNCH = 10, /* split md_step into launches of at most k steps */
-    MD_OPT_TRACE = 11           /* 1: record one md_trace_rec per work item of the next md_step */
+    MD_OPT_TRACE = 11,          /* 1: record one md_trace_rec per work item of the next md_step */
+    MD_OPT_CELL_CAPACITY = 12   /* atoms a cell may hold, 1..64 (default 64): a load or step that
+                                   puts more atoms in a cell fails with MD_ECAPACITY (forces the
+                                   capacity guard in tests) */
 };
 
 enum md_claim_order {
@@ -175,7 +178,7 @@ int md_set_option(md_sim *s, int key, int64_t value);
 
 /* Velocity-scaling thermostat (Sec. 4: kernels md_thermo_a/md_thermo_b compute a scale
  * factor from the new velocities and md_v3b applies it before the positions advance;
- * Sec. 5 simulates the canonical ensemble with it).  With temperature T0 > 0 every
+ * Sec. 4.2 simulates the canonical ensemble with it).  With temperature T0 > 0 every
  * later step starts by scaling the velocities v(t) of the atoms of each slice i by
  *     lambda_i = sqrt(3 n_i T0 / (2 K_i)),   K_i = sum over the slice of |v(t)|^2 / 2,
  * (lambda_i = 1 when the slice holds no atoms or no kinetic energy), so that the
@@ -202,8 +205,23 @@ const char *md_last_error(void);
  * stage order of Table 1: after slice k is integrated, slice k-1 is complete.  Host-only. */
 int md_claim_table(int slices, int order, uint64_t seed, uint16_t *out);
 
-/* Device bytes md_init + md_load would allocate for this system (for admission). */
+/* Device bytes a served run of this system holds at most (the admission measure): two
+ * cell buffers of 3328 B per cell, cell and slice counters, the larger of the load copies
+ * and the read-back outputs (72 B per atom), the read-back energy partials, and the launch
+ * scratch of one 64-step packed launch with 32 cells per work item (work queue, energy
+ * partials, migration log).  -1 for an invalid geometry. */
 int64_t md_footprint_bytes(const double box[3], int slices, double rc, int64_t n);
+
+/* Device memory allocator used for every later device allocation of the library (NULL,
+ * NULL: hipMalloc / hipFree, the default).  alloc(bytes, ctx) returns device memory of
+ * the current device aligned to at least 256 bytes, or NULL (MD_ENOMEM); release(ptr,
+ * ctx) gives it back once the library has synchronised every stream that used it, e.g.
+ * torch's caching allocator.  Both are called from the thread that calls into the
+ * library, or from an md_server's own thread.  MD_ESTATE while any md_sim or md_server
+ * exists; MD_EINVAL when only one of the two functions is given. */
+typedef void *(*md_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*md_free_fn)(void *ptr, void *ctx);
+int md_set_allocator(md_alloc_fn alloc, md_free_fn release, void *ctx);
 
 /* ---------------------------------------------------------------------------
  * Serving: independent runs arrive at any time, are admitted first-come
@@ -222,7 +240,9 @@ typedef struct md_run_desc {
     int64_t steps;
     int64_t energy_every;      /* sample interval (0: only t = 0 and t = steps) */
     uint64_t tag;              /* caller's label, returned in md_result */
-    int32_t keep_state;        /* 1: keep the final state for md_fetch_state */
+    int32_t keep_state;        /* 1: keep the final state for md_fetch_state (the library
+                                  never writes into caller memory after md_submit returns;
+                                  the caller copies the state out when it wants it) */
 } md_run_desc;
 
 typedef struct md_result {
@@ -235,6 +255,9 @@ typedef struct md_result {
     double t_submit, t_admit, t_done; /* seconds on the server's clock */
 } md_result;
 
+/* Runs that may wait for admission at once; md_submit returns MD_EBUSY beyond. */
+#define MD_SERVER_MAX_QUEUED 4096
+
 enum md_server_flags {
     MD_SERVER_FAKE_EXECUTOR = 1  /* no GPU: runs complete after a simulated time (tests) */
 };
@@ -245,7 +268,8 @@ int md_server_create(size_t hbm_budget_bytes, int max_runs, md_server **out);
 int md_server_create_ex(size_t hbm_budget_bytes, int max_runs, int quantum_steps, int flags,
                         md_server **out);
 /* Copy the run and queue it; *ticket identifies it.  MD_EINVAL for an invalid run,
- * MD_ENOMEM when its footprint exceeds the whole budget. */
+ * MD_ENOMEM when its footprint (md_footprint_bytes with the server's quantum) exceeds
+ * the whole budget, MD_EBUSY when MD_SERVER_MAX_QUEUED runs already wait. */
 int md_submit(md_server *sv, const md_run_desc *run, uint64_t *ticket);
 /* MD_PENDING while queued or running; MD_OK when done (result filled); the run's
  * own error code if it failed (result filled).  A finished ticket is released by

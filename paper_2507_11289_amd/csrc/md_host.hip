@@ -141,21 +141,56 @@ static int make_geom(const double box[3], int slices, double rc, double dt, int 
   g->cps = (int)cps;
   g->ncell = (int)ncell;
   g->prec = prec;
+  g->cap = CELL_CAP;
   return MD_OK;
 }
 
-static int64_t footprint(const DGeom& g, int64_t n) {
-  int64_t b = 2ll * g.ncell * CELL_BYTES;    // cell buffers
-  b += 4ll * g.ncell * 4;                    // ncnt, nin x2
-  b += 64ll * g.S + 4096;                    // counters, logs
-  b += 2ll * 3 * 8 * n;                      // staging of md_load (pos, vel)
+// Finalise items per slice and step are the force items' count divided by this (rounded
+// up) under the dataflow scheduler.
+constexpr int64_t FINALISE_MERGE = 4;
+// Served runs: cells per work item (short items keep each step's critical path short)
+// and steps per packed launch when the server is given no quantum.
+constexpr int64_t SERVED_CHUNK_CELLS = 32;
+constexpr int64_t SERVED_QUANTUM = 64;
+
+static int64_t finalise_items(int64_t nch) {
+  return std::max<int64_t>(1, (nch + FINALISE_MERGE - 1) / FINALISE_MERGE);
+}
+
+// Device bytes of one simulation with `nch` force items per slice, advanced in launches of
+// at most `launch_steps` steps: the resident state plus the largest transient buffers.
+//   resident: two cell buffers, the cell counters of both parities, per-slice counters,
+//     cumulative migrations, claim table;
+//   transient, never at the same time: the load copies (pos, vel) or the read-back outputs
+//     (pos, vel, force), at most 72 B per atom, plus the read-back energy partials;
+//   per launch: the work queue (8 B per item), the energy partials of one sample, the
+//     migration log of every step of the launch;
+//   thermostat: the forces kept between force and integrate items (24 B per slot) and the
+//     per-item kinetic energies.
+static int64_t footprint(const DGeom& g, int64_t n, int64_t nch, int64_t launch_steps, bool thermo) {
+  int64_t b = 2ll * g.ncell * CELL_BYTES;
+  b += 4ll * g.ncell * 4;
+  b += 64ll * g.S + 4096;
+  b += 3ll * 3 * 8 * n + 3ll * 8 * sync_blocks(g);
+  const int64_t ips = g.S * (nch + finalise_items(nch) + (thermo ? nch : 0));
+  b += launch_steps * ips * 8;
+  b += 3ll * 8 * g.S * nch;
+  b += 2ll * 4 * g.S * launch_steps;
+  if (thermo) b += (int64_t)g.ncell * 3 * CELL_CAP * 8 + 16ll * g.S * nch;
   return b;
+}
+
+static int auto_chunks(const DGeom& g, int64_t chunk_cells, int64_t n_atoms);
+
+// Footprint of a served run: SERVED_CHUNK_CELLS cells per item, `quantum` steps per launch.
+static int64_t served_footprint(const DGeom& g, int64_t n, int64_t quantum) {
+  return footprint(g, n, auto_chunks(g, SERVED_CHUNK_CELLS, n), quantum > 0 ? quantum : SERVED_QUANTUM, false);
 }
 
 extern "C" int64_t md_footprint_bytes(const double box[3], int slices, double rc, int64_t n) {
   DGeom g;
   if (make_geom(box, slices, rc, 1.0, MD_FP64, &g) != MD_OK) return -1;
-  return footprint(g, n);
+  return served_footprint(g, n, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -222,22 +257,65 @@ extern "C" int md_claim_table(int slices, int order, uint64_t seed, uint16_t* ou
 // ---------------------------------------------------------------------------
 // device buffers of one simulation / run
 // ---------------------------------------------------------------------------
+// Device memory comes from hipMalloc, or from the caller's allocator (md_set_allocator),
+// which may only change while no simulation or server exists.
+static md_alloc_fn g_alloc = nullptr;
+static md_free_fn g_free = nullptr;
+static void* g_alloc_ctx = nullptr;
+static std::atomic<int> g_live{0};  // simulations and servers alive
+static std::mutex g_alloc_mu;
+
+// Counts a handle as alive from its creation on; a failed creation gives the count back.
+struct LiveGuard {
+  bool keep = false;
+  LiveGuard() { g_live++; }
+  ~LiveGuard() {
+    if (!keep) g_live--;
+  }
+};
+
+extern "C" int md_set_allocator(md_alloc_fn alloc, md_free_fn release, void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(MD_EINVAL, "give both an allocation and a release function, or neither");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (g_live.load() != 0)
+    return fail(MD_ESTATE, "%d simulations or servers still hold device memory", g_live.load());
+  g_alloc = alloc;
+  g_free = release;
+  g_alloc_ctx = alloc ? ctx : nullptr;
+  return MD_OK;
+}
+
 template <class T>
 static int dalloc(T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  const size_t bytes = count * sizeof(T);
+  if (g_alloc) {
+    void* q = g_alloc(bytes, g_alloc_ctx);
+    if (!q) return fail(MD_ENOMEM, "the caller's allocator returned no memory for %zu bytes", bytes);
+    if (reinterpret_cast<uintptr_t>(q) % 256 != 0) {
+      g_free(q, g_alloc_ctx);
+      return fail(MD_EINVAL, "the caller's allocator returned memory not aligned to 256 bytes");
+    }
+    *p = static_cast<T*>(q);
+    return MD_OK;
+  }
+  hipError_t e = hipMalloc((void**)p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
-    return fail(MD_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+    return fail(MD_ENOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
   }
   return MD_OK;
 }
 
 template <class T>
 static void dfree(T*& p) {
-  if (p) (void)hipFree((void*)p);
+  if (p) {
+    if (g_free) g_free((void*)p, g_alloc_ctx);
+    else (void)hipFree((void*)p);
+  }
   p = nullptr;
 }
 
@@ -401,10 +479,6 @@ static int device_ready() {
   return MD_OK;
 }
 
-// Finalise items per slice and step are the force items' count divided by this (rounded
-// up) under the dataflow scheduler.
-constexpr int64_t FINALISE_MERGE = 4;
-
 // Work items per slice and phase.  Without a given cell count an item holds about
 // ATOMS_PER_ITEM atoms (at least 32 cells): fewer, larger items mean fewer queue
 // operations and fewer L2 invalidations at item start, more and smaller ones balance
@@ -445,6 +519,7 @@ extern "C" void md_free(md_sim* s) {
   free_launch_scratch(s);
   if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
   delete s;
+  g_live--;
 }
 
 extern "C" int md_init(const double box[3], int slices, double rc, double dt, int precision,
@@ -455,6 +530,7 @@ extern "C" int md_init(const double box[3], int slices, double rc, double dt, in
   int rc_ = make_geom(box, slices, rc, dt, precision, &g);
   if (rc_) return rc_;
   if ((rc_ = device_ready())) return rc_;
+  LiveGuard live;
   std::unique_ptr<md_sim> s(new md_sim());
   s->g = g;
   s->rc = rc;
@@ -470,6 +546,7 @@ extern "C" int md_init(const double box[3], int slices, double rc, double dt, in
   s->ls = new LaunchScratch();
   s->nch = auto_chunks(g, 0, 0);
   *out = s.release();
+  live.keep = true;
   return MD_OK;
 }
 
@@ -529,6 +606,10 @@ extern "C" int md_set_option(md_sim* s, int key, int64_t value) {
     case MD_OPT_TRACE:
       s->trace_on = value != 0;
       return MD_OK;
+    case MD_OPT_CELL_CAPACITY:
+      if (value < 1 || value > CELL_CAP) return fail(MD_EINVAL, "cell capacity must be in [1, %d]", CELL_CAP);
+      s->g.cap = (int)value;
+      return MD_OK;
     case MD_OPT_MAX_STEPS_PER_LAUNCH:
       if (value <= 0) return fail(MD_EINVAL, "max steps per launch must be > 0");
       s->max_steps_per_launch = value;
@@ -567,7 +648,7 @@ static int err_status(uint32_t w) {
 }
 
 static const char* err_text(uint32_t w) {
-  if (w & ERR_CAPACITY) return "a cell exceeded its 64 atom slots";
+  if (w & ERR_CAPACITY) return "a cell exceeded its atom slots (MD_OPT_CELL_CAPACITY, at most 64)";
   if (w & ERR_WATCHDOG) return "a dependency wait exceeded the watchdog budget";
   if (w & ERR_DISPLACEMENT) return "an atom moved by more than one slice in one step";
   if (w & ERR_NONFINITE) return "non-finite position, velocity or force";
@@ -724,7 +805,7 @@ static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st
   // finalise items: a quarter as many as force items under the dataflow scheduler (each
   // is short and every item pays a release and an acquire); as many with a fixed claim
   // order, whose tickets enumerate equal chunk counts for both phases
-  ra->nchA = dataflow ? (int)std::max<int64_t>(1, (s->nch + FINALISE_MERGE - 1) / FINALISE_MERGE) : s->nch;
+  ra->nchA = dataflow ? (int)finalise_items(s->nch) : s->nch;
   ra->every = (int)s->every;
   ra->count = s->count_pairs ? 1 : 0;
   ra->fail_at = s->fail_at;
@@ -1080,7 +1161,7 @@ extern "C" int md_get_stats(md_sim* s, md_stats* out) {
   out->slices = s->g.S;
   out->ncx = s->g.ncx;
   for (int d = 0; d < 3; d++) out->grid[d] = s->g.G[d];
-  out->cell_capacity = CELL_CAP;
+  out->cell_capacity = s->g.cap;
   out->ncell = s->g.ncell;
   if (s->loaded) {
     std::vector<unsigned long long> m((size_t)2 * s->g.S);
@@ -1180,7 +1261,6 @@ static void finish_served(md_server* sv, const std::shared_ptr<ServedRun>& r, in
 }
 
 // Bring an admitted run onto the device: geometry, binning, energy at t = 0.
-constexpr int64_t SERVED_CHUNK_CELLS = 32;
 
 static int admit_served(md_server* sv, ServedRun& r) {
   if (sv->flags & MD_SERVER_FAKE_EXECUTOR) return MD_OK;
@@ -1274,7 +1354,7 @@ static void server_loop(md_server* sv) {
         const int64_t t = fake ? r->res.steps_done : r->sim->t;
         const int64_t left = r->d.steps - t;
         if (left <= 0) continue;
-        const int64_t q = sv->quantum > 0 ? sv->quantum : 64;
+        const int64_t q = sv->quantum > 0 ? sv->quantum : SERVED_QUANTUM;
         int64_t k = std::min(left, q);
         // launches end at the run's energy-sampling steps, which are then taken by a
         // read-back pass: every launch runs the plain kernel variant
@@ -1329,6 +1409,7 @@ extern "C" int md_server_create_ex(size_t hbm_budget_bytes, int max_runs, int qu
   if (!out) return fail(MD_EINVAL, "out is NULL");
   *out = nullptr;
   if (hbm_budget_bytes == 0 || max_runs < 1 || quantum_steps < 0) return fail(MD_EINVAL, "bad server limits");
+  LiveGuard live;
   std::unique_ptr<md_server> sv(new md_server());
   sv->budget = hbm_budget_bytes;
   sv->max_runs = max_runs;
@@ -1341,6 +1422,7 @@ extern "C" int md_server_create_ex(size_t hbm_budget_bytes, int max_runs, int qu
     HIPCHK(hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking));
   }
   md_server* p = sv.release();
+  live.keep = true;
   p->th = std::thread(server_loop, p);
   *out = p;
   return MD_OK;
@@ -1361,13 +1443,15 @@ extern "C" int md_submit(md_server* sv, const md_run_desc* run, uint64_t* ticket
   auto r = std::make_shared<ServedRun>();
   r->d = *run;
   r->d.pos = r->d.vel = nullptr;
-  r->fp = footprint(g, run->n);
+  r->fp = served_footprint(g, run->n, sv->quantum);
   if (r->fp > (int64_t)sv->budget)
     return fail(MD_ENOMEM, "run needs %lld device bytes, budget is %zu", (long long)r->fp, sv->budget);
   r->pos.assign(run->pos, run->pos + 3 * run->n);
   r->vel.assign(run->vel, run->vel + 3 * run->n);
   r->res.tag = run->tag;
   std::lock_guard<std::mutex> lk(sv->mu);
+  if ((int64_t)sv->queue.size() >= MD_SERVER_MAX_QUEUED)
+    return fail(MD_EBUSY, "%d runs already wait for admission", MD_SERVER_MAX_QUEUED);
   r->ticket = sv->next_ticket++;
   r->res.t_submit = sv->now();
   sv->runs[r->ticket] = r;
@@ -1435,5 +1519,6 @@ extern "C" int md_server_destroy(md_server* sv) {
   sv->ls.release();
   if (sv->stream) (void)hipStreamDestroy(sv->stream);
   delete sv;
+  g_live--;
   return MD_OK;
 }

@@ -50,6 +50,7 @@ struct DGeom {
   int cps;         // cells per slice
   int ncell;       // cells in total
   int prec;        // 0 FP64, 1 FP32 force
+  int cap;         // atoms a cell may hold (at most CELL_CAP; lower to force capacity errors)
 };
 
 struct RunArgs {

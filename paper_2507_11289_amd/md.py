@@ -19,9 +19,13 @@ MD_ECAPACITY, MD_EUNSTABLE, MD_ENOTFOUND, MD_EBUSY, MD_EWATCHDOG = -5, -6, -7, -
 MD_FP64, MD_FP32_FORCE = 0, 1
 OPT_ENERGY_EVERY, OPT_CLAIM_ORDER, OPT_ORDER_SEED, OPT_MIGRATION_LOG = 1, 2, 3, 4
 OPT_CHUNK_CELLS, OPT_COUNT_PAIRS, OPT_WATCHDOG_MS, OPT_GRID = 5, 6, 7, 8
-OPT_FAIL_AT_STEP, OPT_MAX_STEPS_PER_LAUNCH, OPT_TRACE = 9, 10, 11
+OPT_FAIL_AT_STEP, OPT_MAX_STEPS_PER_LAUNCH, OPT_TRACE, OPT_CELL_CAPACITY = 9, 10, 11, 12
 ORDER_SWEEP, ORDER_PHASED, ORDER_DESCENDING, ORDER_RANDOM, ORDER_DATAFLOW = 0, 1, 2, 3, 4
 SERVER_FAKE_EXECUTOR = 1
+SERVER_MAX_QUEUED = 4096
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class md_stats(C.Structure):
@@ -95,6 +99,7 @@ _SIGS = {
     "md_fetch_state": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "md_server_stats": ([C.c_void_p] + [C.POINTER(C.c_int64)] * 5, C.c_int),
     "md_server_destroy": ([C.c_void_p], C.c_int),
+    "md_set_allocator": ([ALLOC_FN, FREE_FN, C.c_void_p], C.c_int),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -153,6 +158,32 @@ def md_claim_table(slices: int, order: int, seed: int = 1) -> np.ndarray:
     _check(lib().md_claim_table(int(slices), int(order), int(seed), t.ctypes.data_as(C.POINTER(C.c_uint16))),
            "md_claim_table")
     return np.stack([t >> 15, t & 0x7FFF], axis=1).astype(np.int64)
+
+
+_allocator_refs = None
+
+
+def set_allocator(alloc=None, release=None):
+    """md_set_allocator with Python callables alloc(bytes) -> int address and
+    release(address); None, None returns to hipMalloc / hipFree."""
+    global _allocator_refs
+    if alloc is None and release is None:
+        _check(lib().md_set_allocator(ALLOC_FN(), FREE_FN(), None), "md_set_allocator")
+        _allocator_refs = None
+        return
+    a = ALLOC_FN(lambda nbytes, ctx: alloc(int(nbytes)) or None)
+    f = FREE_FN(lambda ptr, ctx: release(int(ptr)))
+    _check(lib().md_set_allocator(a, f, None), "md_set_allocator")
+    _allocator_refs = (a, f)  # the library keeps calling them: keep them alive
+
+
+def use_torch_allocator():
+    """Back every later device allocation of the library with torch's caching allocator
+    on the current device."""
+    import torch
+
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n),
+                  lambda p: torch.cuda.caching_allocator_delete(p))
 
 
 class Sim:

@@ -143,3 +143,42 @@ def test_fake_server_slot_cap_and_late_arrivals():
         assert min(done[t].t_admit for t in t1) < max(done[t].t_done for t in t0)
     finally:
         sv.close()
+
+
+def test_server_queue_limit_returns_busy():
+    """At most MD_SERVER_MAX_QUEUED runs wait for admission; the next submission gets
+    MD_EBUSY (fake executor: one long resident run, nothing else is admitted)."""
+    box, pos, vel, _ = inputs.homogeneous(400, 0.8, 1.0, 3)
+    slices = int(box[0] // 2.5)
+    sv = md.Server(1 << 40, 1, quantum_steps=50, flags=md.SERVER_FAKE_EXECUTOR)
+    try:
+        sv.submit(box, slices, pos, vel, 10 ** 9)
+        time.sleep(0.05)
+        k = 0
+        with pytest.raises(md.MDError) as e:
+            for k in range(md.SERVER_MAX_QUEUED + 2):
+                sv.submit(box, slices, pos, vel, 10)
+        assert e.value.code == md.MD_EBUSY
+        assert md.SERVER_MAX_QUEUED - 1 <= k <= md.SERVER_MAX_QUEUED
+        assert sv.stats()["queued"] >= md.SERVER_MAX_QUEUED - 1
+    finally:
+        sv.close()
+
+
+def test_allocator_hook_rules():
+    L = md.lib()
+    # only one of the two functions: invalid
+    a = md.ALLOC_FN(lambda n, c: None)
+    assert L.md_set_allocator(a, md.FREE_FN(), None) == md.MD_EINVAL
+    # no handle alive: setting and clearing succeed
+    md.set_allocator(lambda n: 0, lambda p: None)
+    md.set_allocator(None, None)
+    # a live server (fake executor) blocks changes
+    sv = md.Server(1 << 30, 1, flags=md.SERVER_FAKE_EXECUTOR)
+    try:
+        with pytest.raises(md.MDError) as e:
+            md.set_allocator(lambda n: 0, lambda p: None)
+        assert e.value.code == md.MD_ESTATE
+    finally:
+        sv.close()
+    md.set_allocator(None, None)
