@@ -105,13 +105,58 @@ def test_fp32_force_trajectory_tracks_fp64(c0):
         elog = sim.energy_log()
         U, K, W = sim.energy_virial()
         pos, vel, F = sim.state()
+        cells = sim.cells()
+        counts = sim.slice_counts()
     E = elog[:, 1] + elog[:, 2]
     Eo = o["elog"][:10, 1] + o["elog"][:10, 2]
     # 1e-5-accurate forces keep the short trajectory within 1e-6 per atom
     assert np.abs(E - Eo).max() / c0.n < 1e-6
     c = ref.forces_cells(g, pos)
     assert ref.force_error(F, c["F"], c["scale"]).max() <= 1e-5
-    _, _, ocell = ref.bin_atoms(g, pos)
+    # the GPU's binning of its own positions after 100 steps follows the binning rule
+    _, osl, ocell = ref.bin_atoms(g, pos)
+    np.testing.assert_array_equal(cells, ocell)
+    np.testing.assert_array_equal(counts, np.bincount(osl, minlength=c0.slices))
+
+
+def migrations_from_binning(g, p0, p1):
+    """Per-slice (left, right) migration counts of one step from the oracle's binning of
+    the positions before and after it."""
+    s0 = ref.bin_atoms(g, p0)[1].astype(np.int64)
+    s1 = ref.bin_atoms(g, p1)[1].astype(np.int64)
+    delta = (s1 - s0) % g.S
+    assert np.isin(delta, [0, 1, g.S - 1]).all()
+    out = np.zeros((g.S, 2), np.int64)
+    np.add.at(out[:, 0], s0[delta == g.S - 1], 1)
+    np.add.at(out[:, 1], s0[delta == 1], 1)
+    return out
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_migration_log_step_by_step_against_oracle_binning(c0, prec):
+    """Each step's per-slice migration counts equal the oracle's binning of the GPU's own
+    positions before and after the step (bit-exact); so do cells and slice counts."""
+    say(f"[gpu] lj_fluid_2048 migration log step by step, precision={prec}")
+    g = ref.geometry(c0.box, c0.slices, c0.rc)
+    # a hotter copy of the fluid so that atoms cross slice boundaries every few steps
+    vel = 4.0 * c0.vel
+    total = 0
+    with md.Sim(c0.box, c0.slices, c0.rc, c0.dt, prec) as sim:
+        sim.set_option(md.OPT_MIGRATION_LOG, 1)
+        sim.load(c0.pos, vel)
+        p0 = c0.pos
+        for t in range(25):
+            sim.step(1)
+            p1, _, _ = sim.state()
+            mig = sim.migration_log()
+            assert mig.shape == (1, c0.slices, 2)
+            np.testing.assert_array_equal(mig[0], migrations_from_binning(g, p0, p1))
+            _, osl, ocell = ref.bin_atoms(g, p1)
+            np.testing.assert_array_equal(sim.cells(), ocell)
+            np.testing.assert_array_equal(sim.slice_counts(), np.bincount(osl, minlength=c0.slices))
+            total += int(mig.sum())
+            p0 = p1
+    assert total > 20
 
 
 def test_brute_force_tiny_systems():
@@ -368,3 +413,107 @@ def test_errors_are_reported_and_poison():
         with pytest.raises(md.MDError) as e:
             sim.step(1)
         assert e.value.code == md.MD_ESTATE
+
+
+def test_cutoff_decisions_without_fused_r2():
+    """Pairs whose squared distance is within ulps of rc^2 and whose decision a fused
+    multiply-add in r^2 would flip: the FP64 decision (every pair in FP64 mode, the
+    guard band in FP32-force mode) must be the unfused one of the oracle."""
+    from tests.cutoff_cases import flip_separations, isolated_pair_system, r2_unfused
+    seps = flip_separations(48)
+    box, pos = isolated_pair_system(seps)
+    g = ref.geometry(box, 3, 2.5)
+    inside = np.array([r2_unfused(d) <= 6.25 for d in seps])
+    Fb, Ub, Wb, Pb = ref.forces_brute(g, pos)
+    c = ref.forces_cells(g, pos)
+    assert Pb == int(inside.sum()) and 0 < Pb < len(seps)
+    vel = np.zeros_like(pos)
+    for prec in PRECS:
+        say(f"[gpu] {len(seps)} pairs at rc^2 within ulps, {Pb} in range, precision={prec}")
+        with md.Sim(box, 3, 2.5, 0.005, prec) as sim:
+            sim.set_option(md.OPT_COUNT_PAIRS, 1)
+            sim.load(pos, vel)
+            _, _, F = sim.state()
+            out = np.repeat(~inside, 2)
+            np.testing.assert_array_equal(F[out], 0.0)
+            assert (np.abs(F[~out]).sum(axis=1) > 0).all()
+            assert ref.force_error(F, Fb, c["scale"]).max() <= TOL[prec]
+            sim.step(1)
+            assert sim.stats().in_range == 2 * Pb
+
+
+@pytest.mark.parametrize("order,thermo", [(None, 0.0), (md.ORDER_RANDOM, 0.0), (None, 1.2)])
+def test_trace_has_no_races(medium, order, thermo):
+    """Race detection: every work item of two persistent launches ran exactly once and
+    became ready only after every item whose results it reads had finished (device clock
+    of the per-item trace)."""
+    from paper_2507_11289_amd import tracecheck
+    say(f"[gpu] trace race check order={order} thermostat={thermo}")
+    with md.Sim(medium.box, medium.slices, medium.rc, medium.dt, md.MD_FP32_FORCE) as sim:
+        if order is not None:
+            sim.set_option(md.OPT_CLAIM_ORDER, order)
+            sim.set_option(md.OPT_ORDER_SEED, 3)
+        if thermo:
+            sim.set_thermostat(thermo)
+        sim.set_option(md.OPT_TRACE, 1)
+        sim.set_option(md.OPT_MAX_STEPS_PER_LAUNCH, 6)
+        sim.load(medium.pos, medium.vel)
+        sim.step(12)
+        rec, hz = sim.trace()
+        st = sim.stats()
+    assert st.last_launches == 2 and hz > 0
+    rep = tracecheck.check(rec, medium.slices)
+    say(f"    {rep['items']} items, {rep['launches']} launches, violations: {rep['violations']}")
+    assert rep["violations"] == []
+    u = tracecheck.utilisation(rec, st.persistent_grid)
+    say(f"    execute {u['execute']:.3f} wait {u['wait']:.3f} levels {u['levels_in_flight']:.2f}")
+    assert 0.0 < u["execute"] <= 1.0
+
+
+def test_cell_capacity_option_forces_the_guard(c0):
+    """A lowered cell capacity turns a load or a step that fills a cell beyond it into
+    MD_ECAPACITY (the step poisons the handle)."""
+    say("[gpu] capacity option")
+    counts = np.bincount(ref.bin_atoms(ref.geometry(c0.box, c0.slices, c0.rc), c0.pos)[2])
+    with md.Sim(c0.box, c0.slices, c0.rc, c0.dt) as sim:
+        sim.set_option(md.OPT_CELL_CAPACITY, int(counts.max()) - 1)
+        with pytest.raises(md.MDError) as e:
+            sim.load(c0.pos, c0.vel)
+        assert e.value.code == md.MD_ECAPACITY
+    with md.Sim(c0.box, c0.slices, c0.rc, c0.dt) as sim:
+        sim.set_option(md.OPT_CELL_CAPACITY, int(counts.max()))
+        sim.load(c0.pos, c0.vel)
+        assert sim.stats().cell_capacity == counts.max()
+        sim.set_option(md.OPT_CELL_CAPACITY, 2)
+        assert sim.step_rc(1) == md.MD_ECAPACITY
+        assert sim.stats().poisoned == 1
+    with pytest.raises(md.MDError):
+        with md.Sim(c0.box, c0.slices, c0.rc, c0.dt) as sim:
+            sim.set_option(md.OPT_CELL_CAPACITY, 65)
+
+
+def test_torch_caching_allocator_gives_the_same_trajectory(c0):
+    """md_set_allocator with torch's caching allocator: device memory comes from torch
+    (its allocated bytes grow while the simulation lives) and results are bitwise those
+    of the library's own hipMalloc."""
+    import torch
+    say("[gpu] torch caching allocator")
+    with md.Sim(c0.box, c0.slices, c0.rc, c0.dt, md.MD_FP32_FORCE) as sim:
+        sim.load(c0.pos, c0.vel)
+        sim.step(10)
+        want = sim.state()
+    torch.cuda.init()
+    base = torch.cuda.memory_allocated()
+    md.use_torch_allocator()
+    try:
+        with md.Sim(c0.box, c0.slices, c0.rc, c0.dt, md.MD_FP32_FORCE) as sim:
+            sim.load(c0.pos, c0.vel)
+            sim.step(10)
+            got = sim.state()
+            held = torch.cuda.memory_allocated() - base
+        assert held >= 2 * 3328 * (c0.slices * 25)
+        assert torch.cuda.memory_allocated() == base
+    finally:
+        md.set_allocator(None, None)
+    for a, b in zip(want, got):
+        np.testing.assert_array_equal(a, b)

@@ -71,11 +71,25 @@ def test_fluid_4m_binning_counts_and_sampled_forces(fluid4m, prec):
         assert st.in_range == int(full["inr"].sum())
         mig1 = sim.migration_log()
         sim.set_option(md.OPT_COUNT_PAIRS, 0)
-        sim.step(9)
-        mig = np.concatenate([mig1, sim.migration_log()])
+        sim.step(8)
+        mig8 = sim.migration_log()
+        pos9, _, _ = sim.state()
+        sim.step(1)
+        last = sim.migration_log()[-1]
+        mig = np.concatenate([mig1, mig8, last[None]])
         pos, vel, F = sim.state()
-    # the GPU's binning of its own positions after 10 steps
-    _, _, ocell10 = ref.bin_atoms(g, pos)
+        cells10 = sim.cells()
+        counts10 = sim.slice_counts()
+    # the GPU's binning of its own positions after 10 steps, and the last step's
+    # migrations from the binning before and after it
+    _, osl10, ocell10 = ref.bin_atoms(g, pos)
+    np.testing.assert_array_equal(cells10, ocell10)
+    np.testing.assert_array_equal(counts10, np.bincount(osl10, minlength=s.slices))
+    s9 = ref.bin_atoms(g, pos9)[1].astype(np.int64)
+    d9 = (osl10.astype(np.int64) - s9) % s.slices
+    assert np.isin(d9, [0, 1, s.slices - 1]).all()
+    np.testing.assert_array_equal(last[:, 0], np.bincount(s9[d9 == s.slices - 1], minlength=s.slices))
+    np.testing.assert_array_equal(last[:, 1], np.bincount(s9[d9 == 1], minlength=s.slices))
     # forces at t = 10 from the GPU's own FP64 positions
     o10 = ref.forces_subset(g, pos, ids)
     e10 = ref.force_error(F[ids], o10["F"], o10["scale"])
@@ -108,16 +122,34 @@ def test_slab_8m_binning_and_sampled_forces():
         _, _, ocell = ref.bin_atoms(g, s.pos)
         np.testing.assert_array_equal(sim.cells(), ocell)
         sim.set_option(md.OPT_MIGRATION_LOG, 1)
-        sim.step(5)
+        sim.step(4)
+        pos4, _, _ = sim.state()
+        sim.step(1)
         pos, vel, F = sim.state()
         mig = sim.migration_log()
+        cells5 = sim.cells()
+        counts5 = sim.slice_counts()
     o = ref.forces_subset(g, pos, ids)
     e = ref.force_error(F[ids], o["F"], o["scale"])
     n_liq_ids = int((ids < n_l).sum())
     say(f"    t=5 sampled max e_i = {e.max():.3e} (liquid {e[:n_liq_ids].max():.3e}, "
         f"vapour {e[n_liq_ids:].max() if len(ids) > n_liq_ids else 0:.3e})")
     assert e.max() <= TOL[prec]
-    _, _, ocell5 = ref.bin_atoms(g, pos)
+    _, osl5, ocell5 = ref.bin_atoms(g, pos)
+    np.testing.assert_array_equal(cells5, ocell5)
+    np.testing.assert_array_equal(counts5, np.bincount(osl5, minlength=s.slices))
+    # the last step's migrations: the oracle's binning of the GPU's positions before and
+    # after it
+    s4 = ref.bin_atoms(g, pos4)[1].astype(np.int64)
+    d = (osl5.astype(np.int64) - s4) % s.slices
+    assert np.isin(d, [0, 1, s.slices - 1]).all()
+    np.testing.assert_array_equal(mig[-1, :, 0], np.bincount(s4[d == s.slices - 1], minlength=s.slices))
+    np.testing.assert_array_equal(mig[-1, :, 1], np.bincount(s4[d == 1], minlength=s.slices))
+    # slice counts after 5 steps = counts at load + migrations in - migrations out
+    S = s.slices
+    inflow = np.roll(mig[:, :, 1].sum(axis=0), 1) + np.roll(mig[:, :, 0].sum(axis=0), -1)
+    outflow = mig.sum(axis=(0, 2))
+    np.testing.assert_array_equal(counts5, counts + inflow - outflow)
     # migrations happen at every boundary region (liquid and vapour)
     assert mig.sum() > 0
 

@@ -103,6 +103,18 @@ def test_served_run_matches_a_plain_simulation_and_the_oracle():
     g = ref.geometry(s.box, s.slices, s.rc)
     oU, oK, oW = ref.energy(g, s.pos, s.vel)
     assert res.U0 == pytest.approx(oU, rel=1e-12) and res.K0 == pytest.approx(oK, rel=1e-13)
+    # the served end state against the oracle's own FP64 trajectory
+    say(f"[gpu-serve] oracle trajectory, {r.steps} steps")
+    o = ref.run(g, s.pos, s.vel, s.dt, r.steps, every=r.steps)
+    d = p - o["pos"]
+    L = np.array(s.box)
+    d -= L * np.round(d / L)
+    assert np.abs(d).max() < 1e-9
+    np.testing.assert_allclose(v, o["vel"], rtol=0, atol=1e-8)
+    U1o, K1o, W1o = o["elog"][-1, 1:]
+    assert o["elog"][-1, 0] == r.steps
+    assert res.U1 + res.K1 == pytest.approx(U1o + K1o, rel=1e-10)
+    assert res.U1 == pytest.approx(U1o, rel=1e-10) and res.W1 == pytest.approx(W1o, rel=1e-10)
 
 
 @pytest.mark.timeout(300)
