@@ -383,7 +383,7 @@ static double wrap1(double x, double L)
 
 /* ------------------------------------------------------------------------
  * Velocity-scaling thermostat (Sec. 4: a scale factor for the velocities is computed
- * from the new velocities and applied before the positions are advanced; Sec. 5 runs
+ * from the new velocities and applied before the positions are advanced; Sec. 4.2 runs
  * the canonical ensemble with it).  The factor belongs to one slice -- the unit of
  * work the kernels of Sec. 4 process -- and brings that slice's kinetic temperature to
  * the target:  T_s = 2 K_s / (3 n_s),  lambda_s = sqrt(T0 / T_s)

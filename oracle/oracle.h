@@ -83,7 +83,7 @@ int oracle_run(const orc_geom *g, int64_t n, double *pos, double *vel, double *F
                int64_t nsteps, int64_t every, double *elog, int64_t *nsamples,
                int32_t *miglog, int64_t *steps_done);
 
-/* The same trajectory under the velocity-scaling thermostat of Sec. 4 / Sec. 5 at
+/* The same trajectory under the velocity-scaling thermostat of Sec. 4.1 / Sec. 4.2 at
  * temperature T0 > 0: at the start of every step, the velocities v(t) of the atoms of
  * each slice are scaled by lambda_s = sqrt(3 n_s T0 / (2 K_s)) (lambda_s = 1 for a
  * slice without atoms or kinetic energy), slices taken from the positions at t.

@@ -1,5 +1,5 @@
 """GPU parity of the per-slice velocity-scaling thermostat (Sec. 4 kernels md_thermo_a,
-md_thermo_b, md_v3b; Sec. 5 canonical runs) against the oracle, through the C ABI.
+md_thermo_b, md_v3b; Sec. 4.2 canonical runs) against the oracle, through the C ABI.
 
 Bars: exact free-flight closed forms (bitwise); a target equal to the current
 temperature reproduces the NVE run bitwise; FP64 trajectories within the FP64

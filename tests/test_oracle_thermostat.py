@@ -1,5 +1,5 @@
 """Pins of the oracle's per-slice velocity-scaling thermostat (Sec. 4: a factor
-computed from the new velocities scales them before the positions advance; Sec. 5:
+computed from the new velocities scales them before the positions advance; Sec. 4.2:
 canonical-ensemble runs).  The factor of slice s is lambda_s = sqrt(T0 / T_s) with the
 kinetic temperature T_s = 2 K_s / (3 n_s).  Pinned by exact free-flight cases (no
 forces, powers-of-two arithmetic), the defining invariant T_s(lambda v) = T0, slice
