@@ -112,6 +112,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "or python -m paper_2507_11289_amd.build")
+        # One HIP runtime per process: torch ships its own copy of the HIP runtime, and a
+        # library loaded before torch binds to the system copy, after which torch finds no
+        # GPU.  Loaded after torch, libmd binds to torch's copy (same soname), so device
+        # memory and streams can pass between the two (md_set_stream, md_set_allocator).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             fn = getattr(L, name)

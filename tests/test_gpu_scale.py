@@ -123,10 +123,12 @@ def test_slab_8m_binning_and_sampled_forces():
         np.testing.assert_array_equal(sim.cells(), ocell)
         sim.set_option(md.OPT_MIGRATION_LOG, 1)
         sim.step(4)
+        mig4 = sim.migration_log()  # the log covers the last md_step call only
         pos4, _, _ = sim.state()
         sim.step(1)
         pos, vel, F = sim.state()
-        mig = sim.migration_log()
+        mig = np.concatenate([mig4, sim.migration_log()])
+        assert mig.shape == (5, s.slices, 2)
         cells5 = sim.cells()
         counts5 = sim.slice_counts()
     o = ref.forces_subset(g, pos, ids)
