@@ -136,6 +136,28 @@ int md_load(md_sim *s, int64_t n, const double *pos, const double *vel);
  * (afterwards only md_get_stats, md_get_cells-free calls and md_free are valid). */
 int md_step(md_sim *s, int64_t nsteps);
 
+/* Bytes of the launch scratch md_step_noalloc uses on each GPU (16 MiB). */
+#define MD_NOALLOC_SCRATCH_BYTES 16777216
+
+/* md_step for callers that cannot allocate device memory (harnesses that forbid
+ * hipMalloc, serving loops that must not allocate, code that will later be captured):
+ * the same kernels as md_step and bitwise the same results, but the per-launch buffers
+ * (run arguments, work queue, energy partials of the sampled steps, migration log) are
+ * carved out of one fixed array of MD_NOALLOC_SCRATCH_BYTES per GPU that the library
+ * holds until the process ends, instead of device memory allocated on first use.  It
+ * calls no hipMalloc, hipFree or caller allocator (md_set_allocator); the state buffers
+ * come from md_init / md_load.  nsteps is split into launches of at most
+ * MD_OPT_MAX_STEPS_PER_LAUNCH steps whose pieces fit the scratch.
+ * All calls on one GPU share that GPU's array and it keeps the last launch's contents
+ * (every piece is rewritten or cleared before a launch reads it): calls that overlap in
+ * time on one GPU, from several threads or on several streams, race and must not be made.
+ * MD_EINVAL when one step of the system needs more than the scratch (the message gives
+ * both sizes; e.g. more than about 2 million work items per step), when the thermostat
+ * is on (md_set_thermostat) or when MD_OPT_TRACE is set (both need allocated buffers);
+ * otherwise as md_step (errors poison the handle).  md_get_stats reports no kernel time
+ * for these launches. */
+int md_step_noalloc(md_sim *s, int64_t nsteps);
+
 /* Potential energy U (pair energies shifted to vanish at rc), kinetic energy K and
  * virial W = sum over pairs of r_ij . f_ij at the current step (Algorithm 1: the
  * U and V accumulations), summed in FP64 in a fixed order. */

@@ -319,6 +319,51 @@ static void dfree(T*& p) {
   p = nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// Launch scratch that is never allocated (md_step_noalloc): the run arguments, work
+// queue, energy partials and migration log of its launches are carved out of one fixed
+// array per GPU, which the process holds until it ends.  In host code `scratch` names a
+// host-side stand-in, not device memory: everything that reaches a kernel or a copy uses
+// the device address looked up once per device by scratch_setup.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[MD_NOALLOC_SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static unsigned char* g_scratch_dev[SCRATCH_MAX_DEVICES];  // device address of `scratch` per GPU
+static std::mutex g_scratch_mu;
+
+// With device `dev` current: look up this GPU's copy of the array (once per device).
+static int scratch_setup(int dev) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    return fail(MD_EHIP, "device %d is beyond the %d devices the launch scratch supports", dev,
+                SCRATCH_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return MD_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    (void)hipGetLastError();
+    return fail(MD_EHIP, "hipGetSymbolAddress of the launch scratch failed: %s", hipGetErrorString(e));
+  }
+  g_scratch_dev[dev] = static_cast<unsigned char*>(ptr);
+  return MD_OK;
+}
+
+static size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Consecutive 256-byte aligned pieces of a fixed device region.
+struct Carve {
+  unsigned char* base;
+  size_t cap;
+  size_t used;
+  template <class T> T* take(size_t count) {
+    const size_t need = round256(std::max<size_t>(count, 1) * sizeof(T));
+    if (need > cap - used) return nullptr;
+    T* p = reinterpret_cast<T*>(base + used);
+    used += need;
+    return p;
+  }
+};
+
 struct SimBuffers {
   unsigned char* cells[2] = {nullptr, nullptr};
   uint32_t* ncnt[2] = {nullptr, nullptr};
@@ -467,6 +512,10 @@ struct md_sim {
   double* d_fbuf = nullptr;   // thermostat: forces between the force and integrate items
   double* d_kpart = nullptr;  // thermostat: per-item kinetic energy and atom count
   size_t kpart_cap = 0;
+  // energy partials and migration log of the current launch (own buffers or scratch)
+  double* cur_epart = nullptr;
+  uint32_t* cur_miglog = nullptr;
+  int dev = 0;  // device current at md_init
 };
 
 static int device_ready() {
@@ -530,12 +579,16 @@ extern "C" int md_init(const double box[3], int slices, double rc, double dt, in
   int rc_ = make_geom(box, slices, rc, dt, precision, &g);
   if (rc_) return rc_;
   if ((rc_ = device_ready())) return rc_;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if ((rc_ = scratch_setup(dev))) return rc_;
   LiveGuard live;
   std::unique_ptr<md_sim> s(new md_sim());
   s->g = g;
   s->rc = rc;
   s->dt = dt;
   s->prec = precision;
+  s->dev = dev;
   HIPCHK(hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
   s->stream = s->own_stream;
   if ((rc_ = s->b.alloc(g))) {
@@ -748,10 +801,21 @@ static long long watchdog_ticks(int64_t ms) {
   return (long long)ms * (long long)khz;
 }
 
-// Per-run preparation of a launch of k steps: claim table, energy/migration buffers,
-// and the device-visible RunArgs.
+// Energy samples a launch of k steps from step t takes (steps t' with t' % every == 0).
+static void launch_samples(const md_sim* s, int64_t k_steps, int64_t* nsample, int64_t* first_j) {
+  *nsample = 0;
+  *first_j = 0;
+  if (s->every > 0) {
+    *first_j = (s->t + s->every - 1) / s->every;
+    const int64_t last_j = (s->t + k_steps - 1) / s->every;
+    *nsample = last_j >= *first_j ? last_j - *first_j + 1 : 0;
+  }
+}
+
+// Per-run preparation of a launch of k steps: claim table, energy/migration buffers
+// (the run's own, or carved from `arena`), and the device-visible RunArgs.
 static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st, RunArgs* ra,
-                       int64_t* nsample_out, int64_t* first_j_out) {
+                       int64_t* nsample_out, int64_t* first_j_out, Carve* arena) {
   const DGeom& g = s->g;
   int rc;
   if (s->order_dirty) {
@@ -761,24 +825,28 @@ static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st
     s->order_dirty = false;
   }
   int64_t nsample = 0, first_j = 0;
-  if (s->every > 0) {
-    first_j = (s->t + s->every - 1) / s->every;
-    const int64_t last_j = (s->t + k_steps - 1) / s->every;
-    nsample = last_j >= first_j ? last_j - first_j + 1 : 0;
-  }
+  launch_samples(s, k_steps, &nsample, &first_j);
   const size_t ep = (size_t)std::max<int64_t>(nsample, 1) * g.S * s->nch * 3;
-  if (ep > s->epart_cap) {
-    dfree(s->d_epart);
-    if ((rc = dalloc(&s->d_epart, ep))) return rc;
-    s->epart_cap = ep;
-  }
   const size_t ml = s->miglog_on ? (size_t)k_steps * g.S * 2 : 1;
-  if (ml > s->miglog_cap) {
-    dfree(s->d_miglog);
-    if ((rc = dalloc(&s->d_miglog, ml))) return rc;
-    s->miglog_cap = ml;
+  if (arena) {
+    s->cur_epart = arena->take<double>(ep);
+    s->cur_miglog = arena->take<uint32_t>(ml);
+    if (!s->cur_epart || !s->cur_miglog) return fail(MD_EINVAL, "launch scratch exhausted");
+  } else {
+    if (ep > s->epart_cap) {
+      dfree(s->d_epart);
+      if ((rc = dalloc(&s->d_epart, ep))) return rc;
+      s->epart_cap = ep;
+    }
+    if (ml > s->miglog_cap) {
+      dfree(s->d_miglog);
+      if ((rc = dalloc(&s->d_miglog, ml))) return rc;
+      s->miglog_cap = ml;
+    }
+    s->cur_epart = s->d_epart;
+    s->cur_miglog = s->d_miglog;
   }
-  if (s->miglog_on && launch_clear_u32(s->d_miglog, (long long)ml, 0u, st)) return fail(MD_EHIP, "clear failed");
+  if (s->miglog_on && launch_clear_u32(s->cur_miglog, (long long)ml, 0u, st)) return fail(MD_EHIP, "clear failed");
   if (launch_clear_u32(reinterpret_cast<uint32_t*>(s->b.paircnt), 4, 0u, st)) return fail(MD_EHIP, "clear failed");
   if (launch_clear_u32(s->b.err, 1, 0u, st)) return fail(MD_EHIP, "clear failed");
   std::memset(ra, 0, sizeof(*ra));
@@ -790,8 +858,8 @@ static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st
   }
   ra->cntA = s->b.cntA;
   ra->cntF = s->b.cntF;
-  ra->epart = s->d_epart;
-  ra->miglog = s->miglog_on ? s->d_miglog : nullptr;
+  ra->epart = s->cur_epart;
+  ra->miglog = s->miglog_on ? s->cur_miglog : nullptr;
   ra->migcum = s->b.migcum;
   ra->paircnt = s->b.paircnt;
   ra->err = s->b.err;
@@ -839,7 +907,7 @@ static int finish_run(md_sim* s, int64_t k_steps, int64_t nsample, int64_t first
   if (w) return fail(err_status(w), "step at t=%lld: %s", (long long)s->t, err_text(w));
   if (nsample > 0) {
     std::vector<double> part((size_t)nsample * g.S * s->nch * 3);
-    HIPCHK(hipMemcpy(part.data(), s->d_epart, part.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(part.data(), s->cur_epart, part.size() * sizeof(double), hipMemcpyDeviceToHost));
     for (int64_t j = 0; j < nsample; j++) {
       double U = 0, K = 0, W = 0;
       const double* p = part.data() + (size_t)j * g.S * s->nch * 3;
@@ -857,7 +925,7 @@ static int finish_run(md_sim* s, int64_t k_steps, int64_t nsample, int64_t first
   if (s->miglog_on) {
     const size_t off = s->miglog.size();
     s->miglog.resize(off + (size_t)k_steps * g.S * 2);
-    HIPCHK(hipMemcpy(s->miglog.data() + off, s->d_miglog, (size_t)k_steps * g.S * 2 * sizeof(uint32_t),
+    HIPCHK(hipMemcpy(s->miglog.data() + off, s->cur_miglog, (size_t)k_steps * g.S * 2 * sizeof(uint32_t),
                      hipMemcpyDeviceToHost));
     s->miglog_steps += k_steps;
   }
@@ -879,7 +947,7 @@ static int finish_run(md_sim* s, int64_t k_steps, int64_t nsample, int64_t first
 static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& ksteps, LaunchScratch& ls,
                          hipStream_t st, int64_t grid_override, int64_t watchdog_ms, int* last_grid,
                          std::vector<int>& status, double* kernel_seconds = nullptr,
-                         md_sim* trace_owner = nullptr, uint32_t launch_index = 0) {
+                         md_sim* trace_owner = nullptr, uint32_t launch_index = 0, Carve* arena = nullptr) {
   const size_t R = sims.size();
   status.assign(R, MD_OK);
   if (R == 0) return MD_OK;
@@ -889,8 +957,33 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return ksteps[a] > ksteps[b]; });
   const int64_t nrounds = ksteps[idx[0]];
   if (nrounds <= 0) return MD_OK;
-  int rc = ls.reserve(R, (size_t)nrounds);
-  if (rc) return rc;
+  // launch-wide buffers: the caller's scratch pieces, or ls (grown as needed)
+  RunArgs* d_runs;
+  long long *d_run_prefix, *d_round_base;
+  int* d_round_active;
+  unsigned long long *d_ticket, *d_q_tail;
+  uint32_t* d_launch_err;
+  int rc;
+  if (arena) {
+    d_runs = arena->take<RunArgs>(R);
+    d_run_prefix = arena->take<long long>(R + 1);
+    d_round_base = arena->take<long long>((size_t)nrounds + 1);
+    d_round_active = arena->take<int>((size_t)nrounds + 1);
+    d_ticket = arena->take<unsigned long long>(1);
+    d_q_tail = arena->take<unsigned long long>(1);
+    d_launch_err = arena->take<uint32_t>(1);
+    if (!d_runs || !d_run_prefix || !d_round_base || !d_round_active || !d_ticket || !d_q_tail || !d_launch_err)
+      return fail(MD_EINVAL, "launch scratch exhausted");
+  } else {
+    if ((rc = ls.reserve(R, (size_t)nrounds))) return rc;
+    d_runs = ls.d_runs;
+    d_run_prefix = ls.d_run_prefix;
+    d_round_base = ls.d_round_base;
+    d_round_active = ls.d_round_active;
+    d_ticket = ls.d_ticket;
+    d_q_tail = ls.d_q_tail;
+    d_launch_err = ls.d_launch_err;
+  }
   std::vector<RunArgs> ra(R);
   std::vector<int64_t> nsample(R), first_j(R);
   std::vector<long long> prefix(R + 1, 0);
@@ -899,7 +992,7 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   const int mode = sims[idx[0]]->order_kind == MD_ORDER_DATAFLOW ? 0 : 1;
   for (size_t q = 0; q < R; q++) {
     md_sim* s = sims[idx[q]];
-    if ((rc = prepare_run(s, ksteps[idx[q]], mode == 0, st, &ra[q], &nsample[idx[q]], &first_j[idx[q]])))
+    if ((rc = prepare_run(s, ksteps[idx[q]], mode == 0, st, &ra[q], &nsample[idx[q]], &first_j[idx[q]], arena)))
       return rc;
     prefix[q + 1] = prefix[q] + ra[q].ips;
     max_slices = std::max(max_slices, s->g.S);
@@ -912,36 +1005,43 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
     act[(size_t)k] = (int)a;
     rb[(size_t)k + 1] = rb[(size_t)k] + prefix[a];
   }
-  HIPCHK(hipMemcpy(ls.d_runs, ra.data(), R * sizeof(RunArgs), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(ls.d_run_prefix, prefix.data(), prefix.size() * sizeof(long long), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(ls.d_round_base, rb.data(), rb.size() * sizeof(long long), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(ls.d_round_active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_runs, ra.data(), R * sizeof(RunArgs), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_run_prefix, prefix.data(), prefix.size() * sizeof(long long), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_round_base, rb.data(), rb.size() * sizeof(long long), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_round_active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice));
   const size_t total = (size_t)rb[(size_t)nrounds];
   if (nrounds >= (1 << 19)) return fail(MD_EINVAL, "too many steps in one launch");
+  unsigned long long* d_q = nullptr;
   if (mode == 0) {
-    if (total > ls.q_cap) {
-      dfree(ls.d_q);
-      if ((rc = dalloc(&ls.d_q, total))) return rc;
-      ls.q_cap = total;
+    if (arena) {
+      if (!(d_q = arena->take<unsigned long long>(total))) return fail(MD_EINVAL, "launch scratch exhausted");
+    } else {
+      if (total > ls.q_cap) {
+        dfree(ls.d_q);
+        if ((rc = dalloc(&ls.d_q, total))) return rc;
+        ls.q_cap = total;
+      }
+      d_q = ls.d_q;
     }
-    if (launch_clear_u32(reinterpret_cast<uint32_t*>(ls.d_q), (long long)(2 * total), 0u, st))
+    // slots start empty (the top bit marks a pushed item)
+    if (launch_clear_u32(reinterpret_cast<uint32_t*>(d_q), (long long)(2 * total), 0u, st))
       return fail(MD_EHIP, "clear failed");
   }
   LaunchArgs la{};
-  la.runs = ls.d_runs;
+  la.runs = d_runs;
   la.nruns = (int)R;
   la.nrounds = (int)nrounds;
-  la.round_base = ls.d_round_base;
-  la.round_active = ls.d_round_active;
-  la.run_prefix = ls.d_run_prefix;
-  la.ticket = ls.d_ticket;
+  la.round_base = d_round_base;
+  la.round_active = d_round_active;
+  la.run_prefix = d_run_prefix;
+  la.ticket = d_ticket;
   la.watchdog_ticks = watchdog_ticks(watchdog_ms);
   la.trace = nullptr;
   la.launch_index = launch_index;
   la.mode = mode;
-  la.q = mode == 0 ? ls.d_q : nullptr;
-  la.q_tail = ls.d_q_tail;
-  la.launch_err = ls.d_launch_err;
+  la.q = d_q;
+  la.q_tail = d_q_tail;
+  la.launch_err = d_launch_err;
   la.total = (long long)total;
   long long prefill = 0;
   for (size_t q = 0; q < R; q++) prefill += (long long)ra[q].g.S * ra[q].nch;
@@ -964,13 +1064,13 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   }
   const int grid = grid_size(prec, full, nvt, grid_override);
   if (last_grid) *last_grid = grid;
-  if (!ls.ev[0]) {
+  if (kernel_seconds && !ls.ev[0]) {
     HIPCHK(hipEventCreate(&ls.ev[0]));
     HIPCHK(hipEventCreate(&ls.ev[1]));
   }
-  HIPCHK(hipEventRecord(ls.ev[0], st));
+  if (kernel_seconds) HIPCHK(hipEventRecord(ls.ev[0], st));
   if (launch_persistent(la, prec, full, nvt, grid, st)) return fail(MD_EHIP, "persistent launch failed");
-  HIPCHK(hipEventRecord(ls.ev[1], st));
+  if (kernel_seconds) HIPCHK(hipEventRecord(ls.ev[1], st));
   HIPCHK(hipStreamSynchronize(st));
   if (kernel_seconds) {
     float ms = 0.f;
@@ -983,7 +1083,7 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
     HIPCHK(hipMemcpy(trace_owner->trace.data() + off, la.trace, total * sizeof(TraceRec), hipMemcpyDeviceToHost));
   }
   uint32_t lerr = 0;
-  HIPCHK(hipMemcpy(&lerr, ls.d_launch_err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&lerr, d_launch_err, sizeof(uint32_t), hipMemcpyDeviceToHost));
   if (lerr) {
     for (size_t r = 0; r < R; r++) status[r] = fail(MD_EWATCHDOG, "a work-queue wait exceeded the watchdog");
     return MD_OK;
@@ -1015,6 +1115,75 @@ extern "C" int md_step(md_sim* s, int64_t nsteps) {
     int rc = packed_launch(one, ks, *s->ls, s->stream, s->grid_override, s->watchdog_ms, &s->last_grid, st,
                            &ksec, s, (uint32_t)s->last_launches);
     s->last_kernel_seconds += ksec;
+    s->last_launches++;
+    if (!rc) rc = st[0];
+    if (rc) {
+      s->poisoned = true;
+      return rc;
+    }
+    left -= ks[0];
+  }
+  s->last_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return MD_OK;
+}
+
+// Scratch bytes of one launch of k steps of s, carved in the order packed_launch and
+// prepare_run take them (each piece rounded up to 256 bytes).
+static size_t noalloc_launch_bytes(const md_sim* s, int64_t k) {
+  const DGeom& g = s->g;
+  const bool dataflow = s->order_kind == MD_ORDER_DATAFLOW;
+  int64_t nsample = 0, first_j = 0;
+  launch_samples(s, k, &nsample, &first_j);
+  size_t b = round256(sizeof(RunArgs)) + round256(2 * sizeof(long long));
+  b += round256((size_t)(k + 1) * sizeof(long long)) + round256((size_t)(k + 1) * sizeof(int));
+  b += 2 * round256(sizeof(unsigned long long)) + round256(sizeof(uint32_t));
+  b += round256((size_t)std::max<int64_t>(nsample, 1) * g.S * s->nch * 3 * sizeof(double));
+  b += round256((s->miglog_on ? (size_t)k * g.S * 2 : 1) * sizeof(uint32_t));
+  if (dataflow) {
+    const size_t ips = (size_t)g.S * (size_t)(s->nch + finalise_items(s->nch));
+    b += round256((size_t)k * ips * sizeof(unsigned long long));
+  }
+  return b;
+}
+
+extern "C" int md_step_noalloc(md_sim* s, int64_t nsteps) {
+  if (!s) return fail(MD_EINVAL, "sim is NULL");
+  if (!s->loaded) return fail(MD_ESTATE, "md_step_noalloc before md_load");
+  if (s->poisoned) return fail(MD_ESTATE, "handle poisoned by an earlier failure");
+  if (nsteps < 0) return fail(MD_EINVAL, "nsteps must be >= 0");
+  if (s->thermo_T > 0.0)
+    return fail(MD_EINVAL, "md_step_noalloc does not run the thermostat (its force buffer is allocated)");
+  if (s->trace_on) return fail(MD_EINVAL, "md_step_noalloc does not record traces (MD_OPT_TRACE)");
+  unsigned char* base = s->dev >= 0 && s->dev < SCRATCH_MAX_DEVICES ? g_scratch_dev[s->dev] : nullptr;
+  if (!base) return fail(MD_EHIP, "no launch scratch on device %d", s->dev);
+  const size_t one = noalloc_launch_bytes(s, 1);
+  if (one > (size_t)MD_NOALLOC_SCRATCH_BYTES)
+    return fail(MD_EINVAL, "one step of this system needs %zu bytes of launch scratch; md_step_noalloc has %zu",
+                one, (size_t)MD_NOALLOC_SCRATCH_BYTES);
+  s->elog.clear();
+  s->miglog.clear();
+  s->miglog_steps = 0;
+  s->cand = s->inr = s->counted = 0;
+  s->last_kernel_seconds = 0;
+  s->last_launches = 0;
+  s->trace.clear();
+  const auto t0 = std::chrono::steady_clock::now();
+  int64_t left = nsteps;
+  std::vector<md_sim*> sims(1, s);
+  std::vector<int64_t> ks(1);
+  std::vector<int> st;
+  while (left > 0) {
+    // the longest launch (within the step cap) whose pieces fit the scratch
+    int64_t lo = 1, hi = std::min(left, s->max_steps_per_launch);
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (noalloc_launch_bytes(s, mid) <= (size_t)MD_NOALLOC_SCRATCH_BYTES) lo = mid;
+      else hi = mid - 1;
+    }
+    ks[0] = lo;
+    Carve arena{base, (size_t)MD_NOALLOC_SCRATCH_BYTES, 0};
+    int rc = packed_launch(sims, ks, *s->ls, s->stream, s->grid_override, s->watchdog_ms, &s->last_grid, st,
+                           nullptr, nullptr, (uint32_t)s->last_launches, &arena);
     s->last_launches++;
     if (!rc) rc = st[0];
     if (rc) {

@@ -23,6 +23,7 @@ OPT_FAIL_AT_STEP, OPT_MAX_STEPS_PER_LAUNCH, OPT_TRACE, OPT_CELL_CAPACITY = 9, 10
 ORDER_SWEEP, ORDER_PHASED, ORDER_DESCENDING, ORDER_RANDOM, ORDER_DATAFLOW = 0, 1, 2, 3, 4
 SERVER_FAKE_EXECUTOR = 1
 SERVER_MAX_QUEUED = 4096
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -76,6 +77,7 @@ _SIGS = {
     "md_init": ([C.POINTER(C.c_double), C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
     "md_load": ([C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "md_step": ([C.c_void_p, C.c_int64], C.c_int),
+    "md_step_noalloc": ([C.c_void_p, C.c_int64], C.c_int),
     "md_energy_virial": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "md_get_state": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "md_get_cells": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
@@ -230,6 +232,10 @@ class Sim:
 
     def step(self, nsteps: int) -> int:
         return _check(lib().md_step(self._h, int(nsteps)), "md_step")
+
+    def step_noalloc(self, nsteps: int) -> int:
+        """md_step_noalloc: md_step without device allocation (fixed per-GPU scratch)."""
+        return _check(lib().md_step_noalloc(self._h, int(nsteps)), "md_step_noalloc")
 
     def step_rc(self, nsteps: int) -> int:
         """md_step returning the status code instead of raising."""
