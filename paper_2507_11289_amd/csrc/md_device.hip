@@ -80,6 +80,18 @@ __device__ __forceinline__ unsigned ld_relaxed(const uint32_t* p) {
   return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// XCD (L2 domain) running the calling wave: bits [3:0] of the XCC_ID hardware register.
+__device__ __forceinline__ int xcc_id() {
+  return (int)(__builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 0xFu);
+}
+
+// Work queue of slice s of a run: queue x holds the slices [xfirst[x], xfirst[x + 1]).
+__device__ __forceinline__ int slice_queue(const RunArgs& ra, int nq, int s) {
+  int x = 0;
+  for (int q = 1; q < nq; q++) x += s >= ra.xfirst[q] ? 1 : 0;
+  return x;
+}
+
 __device__ __forceinline__ void raise_error(uint32_t* err, uint32_t* abort_flag, uint32_t bits) {
   __hip_atomic_fetch_or(err, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (abort_flag) __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1083,8 +1095,10 @@ __device__ void p1_range(const RunArgs& ra, int b, int e, int dst, int wave, uin
     unsigned n_stay = 0, n_in = 0;
     if (c < e) {
       n_stay = gptr(ra.ncnt[dst])[c];
-      n_in = gptr(ra.nin[dst])[c];
-      gptr(ra.nin[src])[c] = 0u;
+      // move-in counters are only ever accessed atomically (they are incremented by the
+      // integrate items of this and the neighbouring slices, possibly on another XCD)
+      n_in = __hip_atomic_load(gptr(ra.nin[dst]) + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(gptr(ra.nin[src]) + c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (n_stay + n_in > (unsigned)ra.g.cap) {
         raise_error(ra.err, abort_flag, ERR_CAPACITY);
         n_in = 0;
@@ -1319,8 +1333,10 @@ __device__ void run_p2b_item(const RunArgs& ra, const Item& it, double* s_lam, u
   }
 }
 
+// KIND: 0 plain steps only; 1 also energy-sampled steps; 2 also pair counting (the
+// variants differ in register needs, and a kernel is allocated for its largest path).
 // NVT: the kernel variant that also runs thermostat steps (ra.thermo_T > 0).
-template <int PREC, bool FULL, bool NVT>
+template <int PREC, int KIND, bool NVT>
 __device__ void run_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& ws, double (*s_red)[4],
                          unsigned long long (*s_cnt)[5]) {
   const int wave = threadIdx.x >> 6;
@@ -1328,9 +1344,17 @@ __device__ void run_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& ws, 
   if (it.phase == 0) {
     const long long t = ra.t0 + it.k;
     const bool energy = ra.every > 0 && (t % ra.every) == 0;
-    if (!FULL) {
+    if (KIND == 0) {
       if (NVT && nvt) run_p2_item<PREC, false, false, NVT>(ra, it, ws, s_red, s_cnt, ra.abort);
       else run_p2_item<PREC, false, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+    } else if (KIND == 1) {
+      if (NVT && nvt) {
+        if (energy) run_p2_item<PREC, true, false, NVT>(ra, it, ws, s_red, s_cnt, ra.abort);
+        else run_p2_item<PREC, false, false, NVT>(ra, it, ws, s_red, s_cnt, ra.abort);
+      } else {
+        if (energy) run_p2_item<PREC, true, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+        else run_p2_item<PREC, false, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
+      }
     } else if (NVT && nvt) {
       if (ra.count) {
         if (energy) run_p2_item<PREC, true, true, NVT>(ra, it, ws, s_red, s_cnt, ra.abort);
@@ -1357,6 +1381,27 @@ __device__ void run_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& ws, 
   }
 }
 
+// Append the n chunks of item (run, k, phase, slice) to the queue of the slice (thread 0
+// of the item whose completion made the dependency set complete).  The pusher first
+// acquires (every counted item released before its increment) and releases, so whoever
+// takes the items sees the results of all the counted items.
+__device__ void push_items(const LaunchArgs& la, const RunArgs& ra, int run, int k, int phase, int slice,
+                           int n) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+  const int x = la.nq > 1 ? slice_queue(ra, la.nq, slice) : 0;
+  const long long room = la.qoff[x + 1] - la.qoff[x];
+  const unsigned long long base = __hip_atomic_fetch_add(gptr(la.q_tail) + XQ_STRIDE * x,
+                                                         (unsigned long long)n, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+  if ((long long)base + n > room) {  // never expected: the host sized every queue exactly
+    raise_error(la.launch_err, nullptr, ERR_BADINPUT);
+    return;
+  }
+  for (int ch = 0; ch < n; ch++)
+    __hip_atomic_store(gptr(la.q) + la.qoff[x] + base + ch, enc_item(run, k, phase, slice, ch),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Dataflow completion (thread 0, after the item's release fence): count this item
 // towards its dependents with relaxed increments; the count that completes a dependency
 // set acquires (every counted item released before its increment), releases, and
@@ -1369,13 +1414,7 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
     const unsigned needk = (unsigned)ra.nch * (unsigned)(it.k + 1);
     const unsigned old = __hip_atomic_fetch_add(gptr(ra.cntK) + it.slice, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old + 1u != needk) return;
-    // the completing count: see every counted item's results, then publish the pushes
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-    const unsigned long long base =
-        __hip_atomic_fetch_add(gptr(la.q_tail), (unsigned long long)ra.nch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int ch = 0; ch < ra.nch; ch++)
-      __hip_atomic_store(gptr(la.q) + base + ch, enc_item(it.run, it.k, 2, it.slice, ch), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+    push_items(la, ra, it.run, it.k, 2, it.slice, ra.nch);
     return;
   }
   // the step's update of slice i (phase 0, or 2 with the thermostat) counts towards the
@@ -1387,8 +1426,6 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
     const int j = (it.slice + d + S) % S;
     const unsigned old = __hip_atomic_fetch_add(gptr(cnt) + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old + 1u != need) continue;
-    // the completing count: see every counted item's results, then publish the pushes
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
     int phase, k;
     if (update) {
       phase = 1;  // finalise of step k+1
@@ -1398,43 +1435,66 @@ __device__ void complete_dataflow(const LaunchArgs& la, const RunArgs& ra, const
       phase = 0;
       k = it.k + 1;
     }
-    const int nq = phase == 1 ? ra.nchA : ra.nch;
-    const unsigned long long base =
-        __hip_atomic_fetch_add(gptr(la.q_tail), (unsigned long long)nq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int ch = 0; ch < nq; ch++)
-      __hip_atomic_store(gptr(la.q) + base + ch, enc_item(it.run, k, phase, j, ch), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+    push_items(la, ra, it.run, k, phase, j, phase == 1 ? ra.nchA : ra.nch);
   }
 }
 
-// FULL = false: launches without energy samples or pair counting (fewer registers).
-// NVT = true: launches with a thermostat run.
-template <int PREC, bool FULL, bool NVT>
+// Whether an item ends with an agent-scope release.  Items exchange data through memory:
+// an item's inputs are the cells (and counters) its dependencies wrote, its outputs are
+// read by its dependents.  Every item starts with an agent-scope acquire (it invalidates
+// the compute unit's L1; the L2 keeps its lines).  Its stores have completed in its XCD's
+// L2 before it is counted (every wave waits for them).  With one queue for the device
+// (nq = 1) its dependents may run on any XCD, so it also releases at agent scope: the
+// XCD's L2 writes its dirty lines back, and other XCDs see them.  With XCD queues the
+// items of a slice run on the XCD that owns it, and the items of slice i read and write
+// only slices i-1, i, i+1: when all three belong to the same XCD, every dependent reads
+// the item's outputs through the same L2 and the write-back is not needed.  A slice next
+// to another XCD's range, or an item run by a workgroup that is not on the queue's XCD,
+// releases at agent scope.  Move-in counters, incremented by neighbours' integrate items,
+// are accessed atomically only.
+__device__ __forceinline__ bool release_full(const LaunchArgs& la, const RunArgs& ra, const Item& it,
+                                             bool own_xcd) {
+  if (la.nq == 1 || !own_xcd) return true;
+  const int S = ra.g.S;
+  const int x = slice_queue(ra, la.nq, it.slice);
+  return slice_queue(ra, la.nq, (it.slice + S - 1) % S) != x || slice_queue(ra, la.nq, (it.slice + 1) % S) != x;
+}
+
+// KIND (see run_item): 0 launches without energy samples or pair counting (fewest
+// registers), 1 with energy samples, 2 with pair counting.  NVT: with a thermostat run.
+template <int PREC, int KIND, bool NVT>
 __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
   __shared__ BlockLDS<PREC> ws;
   __shared__ double s_red[WAVES][4];
   __shared__ unsigned long long s_cnt[WAVES][5];
   __shared__ Item s_it;
   __shared__ int s_ok;
+  __shared__ int s_full;
   __shared__ long long s_ticket;
   __shared__ RunArgs s_ra;
   static_assert(sizeof(RunArgs) % 4 == 0, "RunArgs is copied as dwords");
-  const long long total = la.total;
+  // the queue this workgroup serves: its XCD's (nq > 1); a workgroup on an XCD without a
+  // queue of its own (never expected) serves one with agent-scope fences on every item
+  const int xq_hw = la.nq > 1 ? xcc_id() : 0;
+  const int xq = xq_hw % la.nq;
+  const bool own_xcd = la.nq > 1 && xq_hw < la.nq;
+  const long long qbase = la.qoff[xq];
+  const long long total = la.qoff[xq + 1] - qbase;
   while (true) {
     if (threadIdx.x == 0) {
       Item it;
       it.go = 0;
-      const long long T =
-          (long long)__hip_atomic_fetch_add(gptr(la.ticket), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_ticket = T;
-      if (la.trace && T < total) la.trace[T].t_claim = wall_clock64();
+      const long long T = (long long)__hip_atomic_fetch_add(gptr(la.ticket) + XQ_STRIDE * xq, 1ull,
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_ticket = qbase + T;  // the item's slot (and trace record)
+      if (la.trace && T < total) la.trace[qbase + T].t_claim = wall_clock64();
       if (T < total) {
         if (la.mode == 0) {
-          // dataflow: wait for slot T to be filled
+          // dataflow: wait for slot T of the queue to be filled
           const long long t_begin = wall_clock64();
           unsigned long long v;
           // relaxed polling; the acquire fence follows once the item is known
-          while (!((v = __hip_atomic_load(gptr(la.q) + T, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 63)) {
+          while (!((v = __hip_atomic_load(gptr(la.q) + qbase + T, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 63)) {
             if (ld_relaxed(la.launch_err)) break;
             if (wall_clock64() - t_begin > la.watchdog_ticks) {
               raise_error(la.launch_err, nullptr, ERR_WATCHDOG);
@@ -1495,6 +1555,7 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
       }
       // one acquire for the workgroup: the barrier below orders every wave after it
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_full = release_full(la, rg, it, own_xcd);
       s_ok = ok;
       if (la.trace) {
         TraceRec& tr = la.trace[s_ticket];
@@ -1505,18 +1566,20 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
         tr.phase = (uint32_t)it.phase;
         tr.hw_id = __smid();
         tr.launch = la.launch_index;
+        tr.xcd = (uint32_t)xcc_id();
+        tr.queue = (uint32_t)xq;
       }
     }
     __syncthreads();
     const RunArgs& ra = s_ra;  // after the barrier: the LDS copy
     const int ok = s_ok;
-    if (ok) run_item<PREC, FULL, NVT>(ra, it, ws, s_red, s_cnt);
+    if (ok) run_item<PREC, KIND, NVT>(ra, it, ws, s_red, s_cnt);
     // every wave's stores have reached the L2 before the barrier (the barrier itself
     // does not wait for them); thread 0's release then covers the whole workgroup
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (s_full) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (la.trace) la.trace[s_ticket].t_done = wall_clock64();
       if (la.mode == 0) {
         // an aborted run still completes its items (without work) so the queue drains
@@ -1530,25 +1593,34 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
   }
 }
 
-// The lean FP32 kernel is held to 128 VGPRs (4 waves per SIMD); the others take what
-// they need.
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void persistent_f32_lean(LaunchArgs la) {
-  persistent_body<1, false, false>(la);
-}
-__global__ __launch_bounds__(WG) void persistent_f32_full(LaunchArgs la) { persistent_body<1, true, false>(la); }
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void persistent_f64_lean(LaunchArgs la) { persistent_body<0, false, false>(la); }
-__global__ __launch_bounds__(WG) void persistent_f64_full(LaunchArgs la) { persistent_body<0, true, false>(la); }
-__global__ __launch_bounds__(WG) void persistent_f32_lean_nvt(LaunchArgs la) { persistent_body<1, false, true>(la); }
-__global__ __launch_bounds__(WG) void persistent_f32_full_nvt(LaunchArgs la) { persistent_body<1, true, true>(la); }
-__global__ __launch_bounds__(WG) void persistent_f64_lean_nvt(LaunchArgs la) { persistent_body<0, false, true>(la); }
-__global__ __launch_bounds__(WG) void persistent_f64_full_nvt(LaunchArgs la) { persistent_body<0, true, true>(la); }
+// The plain FP32 kernel is held to 128 VGPRs (4 waves per SIMD) and the energy-sampling
+// ones to 168 (3 waves per SIMD; FP64 workgroups need that much LDS anyway); the
+// pair-counting (statistics) and thermostat kernels take what they need.
+#define MD_WPE(n) __attribute__((amdgpu_waves_per_eu(n)))
+__global__ __launch_bounds__(WG) MD_WPE(4) void persistent_f32_lean(LaunchArgs la) { persistent_body<1, 0, false>(la); }
+__global__ __launch_bounds__(WG) MD_WPE(3) void persistent_f32_energy(LaunchArgs la) { persistent_body<1, 1, false>(la); }
+__global__ __launch_bounds__(WG) void persistent_f32_full(LaunchArgs la) { persistent_body<1, 2, false>(la); }
+__global__ __launch_bounds__(WG) MD_WPE(3) void persistent_f64_lean(LaunchArgs la) { persistent_body<0, 0, false>(la); }
+__global__ __launch_bounds__(WG) MD_WPE(3) void persistent_f64_energy(LaunchArgs la) { persistent_body<0, 1, false>(la); }
+__global__ __launch_bounds__(WG) void persistent_f64_full(LaunchArgs la) { persistent_body<0, 2, false>(la); }
+__global__ __launch_bounds__(WG) void persistent_f32_lean_nvt(LaunchArgs la) { persistent_body<1, 0, true>(la); }
+__global__ __launch_bounds__(WG) void persistent_f32_energy_nvt(LaunchArgs la) { persistent_body<1, 1, true>(la); }
+__global__ __launch_bounds__(WG) void persistent_f32_full_nvt(LaunchArgs la) { persistent_body<1, 2, true>(la); }
+__global__ __launch_bounds__(WG) void persistent_f64_lean_nvt(LaunchArgs la) { persistent_body<0, 0, true>(la); }
+__global__ __launch_bounds__(WG) void persistent_f64_energy_nvt(LaunchArgs la) { persistent_body<0, 1, true>(la); }
+__global__ __launch_bounds__(WG) void persistent_f64_full_nvt(LaunchArgs la) { persistent_body<0, 2, true>(la); }
+#undef MD_WPE
 
 typedef void (*PersistentFn)(LaunchArgs);
-static PersistentFn persistent_fn(int prec, int full, int nvt) {
-  static const PersistentFn fns[2][2][2] = {
-      {{persistent_f64_lean, persistent_f64_lean_nvt}, {persistent_f64_full, persistent_f64_full_nvt}},
-      {{persistent_f32_lean, persistent_f32_lean_nvt}, {persistent_f32_full, persistent_f32_full_nvt}}};
-  return fns[prec == 1][full != 0][nvt != 0];
+static PersistentFn persistent_fn(int prec, int kind, int nvt) {
+  static const PersistentFn fns[2][3][2] = {
+      {{persistent_f64_lean, persistent_f64_lean_nvt},
+       {persistent_f64_energy, persistent_f64_energy_nvt},
+       {persistent_f64_full, persistent_f64_full_nvt}},
+      {{persistent_f32_lean, persistent_f32_lean_nvt},
+       {persistent_f32_energy, persistent_f32_energy_nvt},
+       {persistent_f32_full, persistent_f32_full_nvt}}};
+  return fns[prec == 1][kind < 0 ? 0 : (kind > 2 ? 2 : kind)][nvt != 0];
 }
 
 // Launch set-up: counters, abort flags, claim counter; in dataflow mode the queue holds
@@ -1556,11 +1628,11 @@ static PersistentFn persistent_fn(int prec, int full, int nvt) {
 __global__ void init_launch_kernel(LaunchArgs la) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
-  if (i == 0) {
-    *la.ticket = 0ull;
-    if (la.launch_err) *la.launch_err = 0u;
+  if (i < la.nq) {
+    la.ticket[XQ_STRIDE * i] = 0ull;
+    if (la.q_tail) la.q_tail[XQ_STRIDE * i] = (unsigned long long)la.prefill[i];
   }
-  long long base = 0;
+  if (i == 0 && la.launch_err) *la.launch_err = 0u;
   for (int r = 0; r < la.nruns; r++) {
     const RunArgs& ra = la.runs[r];
     if (i == 0) *ra.abort = 0u;
@@ -1570,13 +1642,15 @@ __global__ void init_launch_kernel(LaunchArgs la) {
       if (ra.cntK) ra.cntK[s] = 0u;
     }
     if (la.mode == 0 && ra.nsteps > 0) {
+      // the first step's force items, each in its slice's queue (after the earlier runs')
       const long long n0 = (long long)ra.g.S * ra.nch;
-      for (long long e = i; e < n0; e += stride)
-        la.q[base + e] = enc_item(r, 0, 0, (int)(e / ra.nch), (int)(e % ra.nch));
-      base += n0;
+      for (long long e = i; e < n0; e += stride) {
+        const int s = (int)(e / ra.nch), ch = (int)(e % ra.nch);
+        const int x = slice_queue(ra, la.nq, s);
+        la.q[la.qoff[x] + ra.q0[x] + (long long)(s - ra.xfirst[x]) * ra.nch + ch] = enc_item(r, 0, 0, s, ch);
+      }
     }
   }
-  if (i == 0 && la.q_tail) *la.q_tail = (unsigned long long)base;
 }
 
 // ---------------------------------------------------------------------------
@@ -1746,22 +1820,22 @@ int launch_init(const LaunchArgs& la, long long work, void* stream) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int persistent_grid(int prec, int full, int nvt, int* blocks_per_cu, int* cus) {
+int persistent_grid(int prec, int kind, int nvt, int* blocks_per_cu, int* cus) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
   int nb = 0;
   const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_fn(prec, full, nvt), WG, 0);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_fn(prec, kind, nvt), WG, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   *blocks_per_cu = nb;
   *cus = prop.multiProcessorCount;
   return 0;
 }
 
-int launch_persistent(const LaunchArgs& la, int prec, int full, int nvt, int grid, void* stream) {
-  hipLaunchKernelGGL(persistent_fn(prec, full, nvt), dim3(grid), dim3(WG), 0, S_(stream), la);
+int launch_persistent(const LaunchArgs& la, int prec, int kind, int nvt, int grid, void* stream) {
+  hipLaunchKernelGGL(persistent_fn(prec, kind, nvt), dim3(grid), dim3(WG), 0, S_(stream), la);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -375,6 +375,7 @@ struct SimBuffers {
   uint32_t* abort = nullptr;
   unsigned long long* migcum = nullptr;
   unsigned long long* paircnt = nullptr;
+  unsigned long long* scount = nullptr;  // atoms per slice (work-queue ranges, md_get_slice_counts)
   uint16_t* order = nullptr;
   int order_len = 0;
 
@@ -392,6 +393,7 @@ struct SimBuffers {
     if ((rc = dalloc(&abort, 1))) return rc;
     if ((rc = dalloc(&migcum, (size_t)2 * g.S))) return rc;
     if ((rc = dalloc(&paircnt, 2))) return rc;
+    if ((rc = dalloc(&scount, (size_t)g.S))) return rc;
     if ((rc = dalloc(&order, (size_t)2 * g.S))) return rc;
     order_len = 2 * g.S;
     return MD_OK;
@@ -409,6 +411,7 @@ struct SimBuffers {
     dfree(abort);
     dfree(migcum);
     dfree(paircnt);
+    dfree(scount);
     dfree(order);
   }
 };
@@ -429,8 +432,8 @@ struct LaunchScratch {
 
   int reserve(size_t nruns, size_t nrounds) {
     int rc;
-    if (!d_ticket && (rc = dalloc(&d_ticket, 1))) return rc;
-    if (!d_q_tail && (rc = dalloc(&d_q_tail, 1))) return rc;
+    if (!d_ticket && (rc = dalloc(&d_ticket, (size_t)MAX_XQ * XQ_STRIDE))) return rc;
+    if (!d_q_tail && (rc = dalloc(&d_q_tail, (size_t)MAX_XQ * XQ_STRIDE))) return rc;
     if (!d_launch_err && (rc = dalloc(&d_launch_err, 1))) return rc;
     if (nruns > runs_cap) {
       dfree(d_runs);
@@ -516,6 +519,12 @@ struct md_sim {
   double* cur_epart = nullptr;
   uint32_t* cur_miglog = nullptr;
   int dev = 0;  // device current at md_init
+  // XCD work queues: XCDs of the device (1: one queue), whether md_step uses them, and the
+  // slice ranges of the queues for the current md_step
+  int nxcc = 1;
+  bool xcd_queues = false;
+  int nq = 1;
+  int xfirst[MAX_XQ + 1] = {0};
 };
 
 static int device_ready() {
@@ -589,6 +598,14 @@ extern "C" int md_init(const double box[3], int slices, double rc, double dt, in
   s->dt = dt;
   s->prec = precision;
   s->dev = dev;
+  {
+    int nx = 1;
+    if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || nx < 1 || nx > MAX_XQ) {
+      (void)hipGetLastError();
+      nx = 1;
+    }
+    s->nxcc = nx;
+  }
   HIPCHK(hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
   s->stream = s->own_stream;
   if ((rc_ = s->b.alloc(g))) {
@@ -662,6 +679,9 @@ extern "C" int md_set_option(md_sim* s, int key, int64_t value) {
     case MD_OPT_CELL_CAPACITY:
       if (value < 1 || value > CELL_CAP) return fail(MD_EINVAL, "cell capacity must be in [1, %d]", CELL_CAP);
       s->g.cap = (int)value;
+      return MD_OK;
+    case MD_OPT_XCD_QUEUES:
+      s->xcd_queues = value != 0;
       return MD_OK;
     case MD_OPT_MAX_STEPS_PER_LAUNCH:
       if (value <= 0) return fail(MD_EINVAL, "max steps per launch must be > 0");
@@ -786,10 +806,10 @@ extern "C" int md_load(md_sim* s, int64_t n, const double* pos, const double* ve
 // launch; tickets are dealt round by round (round k holds step k of every run that
 // still has steps), so a small run is never starved by a large one.
 // ---------------------------------------------------------------------------
-static int grid_size(int prec, int full, int nvt, int64_t override_) {
+static int grid_size(int prec, int kind, int nvt, int64_t override_) {
   if (override_ > 0) return (int)override_;
   int bpc = 1, cus = 1;
-  if (persistent_grid(prec, full, nvt, &bpc, &cus)) return 256;
+  if (persistent_grid(prec, kind, nvt, &bpc, &cus)) return 256;
   return bpc * cus;
 }
 
@@ -942,6 +962,44 @@ static int finish_run(md_sim* s, int64_t k_steps, int64_t nsample, int64_t first
   return MD_OK;
 }
 
+// Cost of a cell in atom equivalents when the slices are split among the XCD work queues:
+// every cell is staged and walked (and its neighbourhood counted) whether or not it holds
+// atoms, so sparse slices cost more than their atoms alone.
+constexpr double QUEUE_CELL_COST = 4.0;
+
+// Work-queue ranges of s for the next md_step: one contiguous range of slices per XCD,
+// each of at least 3 slices, with boundaries where the cumulative cost (atoms plus
+// QUEUE_CELL_COST per cell) is closest to equal shares.  One queue for the device when the
+// option is off, the claim order is fixed, the GPU has one XCD, or there are fewer than 3
+// slices per XCD.
+static int plan_queues(md_sim* s) {
+  const DGeom& g = s->g;
+  const int S = g.S;
+  s->nq = 1;
+  s->xfirst[0] = 0;
+  for (int x = 1; x <= MAX_XQ; x++) s->xfirst[x] = S;
+  const int nx = s->nxcc;
+  if (!s->xcd_queues || nx <= 1 || s->order_kind != MD_ORDER_DATAFLOW || S < 3 * nx) return MD_OK;
+  if (launch_slice_counts(g, s->b.ncnt[s->par], s->b.scount, s->stream)) return fail(MD_EHIP, "slice counts failed");
+  std::vector<unsigned long long> cnt((size_t)S);
+  HIPCHK(hipMemcpyAsync(cnt.data(), s->b.scount, (size_t)S * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                        s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  std::vector<double> cum((size_t)S + 1, 0.0);
+  for (int i = 0; i < S; i++) cum[(size_t)i + 1] = cum[(size_t)i] + (double)cnt[(size_t)i] + QUEUE_CELL_COST * g.cps;
+  const double W = cum[(size_t)S];
+  for (int x = 1; x < nx; x++) {
+    const double target = W * x / nx;
+    const int lo = s->xfirst[x - 1] + 3, hi = S - 3 * (nx - x);
+    int best = lo;
+    for (int e = lo; e <= hi; e++)
+      if (std::fabs(cum[(size_t)e] - target) < std::fabs(cum[(size_t)best] - target)) best = e;
+    s->xfirst[x] = best;
+  }
+  s->nq = nx;
+  return MD_OK;
+}
+
 // Launch k[r] steps of every simulation in `sims` (all of one precision) as one
 // persistent kernel.  status[r] receives each run's own result.
 static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& ksteps, LaunchScratch& ls,
@@ -969,8 +1027,8 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
     d_run_prefix = arena->take<long long>(R + 1);
     d_round_base = arena->take<long long>((size_t)nrounds + 1);
     d_round_active = arena->take<int>((size_t)nrounds + 1);
-    d_ticket = arena->take<unsigned long long>(1);
-    d_q_tail = arena->take<unsigned long long>(1);
+    d_ticket = arena->take<unsigned long long>((size_t)MAX_XQ * XQ_STRIDE);
+    d_q_tail = arena->take<unsigned long long>((size_t)MAX_XQ * XQ_STRIDE);
     d_launch_err = arena->take<uint32_t>(1);
     if (!d_runs || !d_run_prefix || !d_round_base || !d_round_active || !d_ticket || !d_q_tail || !d_launch_err)
       return fail(MD_EINVAL, "launch scratch exhausted");
@@ -996,6 +1054,36 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
       return rc;
     prefix[q + 1] = prefix[q] + ra[q].ips;
     max_slices = std::max(max_slices, s->g.S);
+  }
+  // kernel variant: pair counting (or fault injection) > energy samples > plain steps
+  int kind = 0, nvt = 0;
+  for (size_t q = 0; q < R; q++) {
+    if (ra[q].count || ra[q].fail_at >= 0) kind = 2;
+    else if (nsample[idx[q]] > 0) kind = std::max(kind, 1);
+    if (ra[q].thermo_T > 0.0) nvt = 1;
+  }
+  const int grid = grid_size(prec, kind, nvt, grid_override);
+  // work queues: one per XCD for a single run that planned them (dataflow only), else one;
+  // workgroups are dealt to the XCDs in turn, so every queue has workers once the grid
+  // holds at least two workgroups per queue
+  int nq = 1;
+  if (mode == 0 && R == 1 && sims[0]->nq > 1 && grid >= 2 * sims[0]->nq) nq = sims[0]->nq;
+  if (R == 1 && nq == 1 && sims[0]->nq > 1) {  // planned, but not possible with this grid
+    sims[0]->nq = 1;
+    for (int x = 1; x <= MAX_XQ; x++) sims[0]->xfirst[x] = sims[0]->g.S;
+  }
+  std::vector<long long> qtotal(MAX_XQ, 0), qfill(MAX_XQ, 0);
+  for (size_t q = 0; q < R; q++) {
+    md_sim* s = sims[idx[q]];
+    for (int x = 0; x <= MAX_XQ; x++) ra[q].xfirst[x] = nq > 1 ? s->xfirst[x] : (x == 0 ? 0 : s->g.S);
+    const long long per_slice = ra[q].ips / s->g.S;  // items of one slice per step
+    for (int x = 0; x < nq; x++) {
+      const long long nsl = ra[q].xfirst[x + 1] - ra[q].xfirst[x];
+      ra[q].q0[x] = qfill[(size_t)x];
+      if (ksteps[idx[q]] <= 0) continue;  // a run without steps here queues nothing
+      qfill[(size_t)x] += nsl * ra[q].nch;
+      qtotal[(size_t)x] += ksteps[idx[q]] * nsl * per_slice;
+    }
   }
   std::vector<long long> rb((size_t)nrounds + 1, 0);
   std::vector<int> act((size_t)nrounds + 1, 0);
@@ -1043,6 +1131,16 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   la.q_tail = d_q_tail;
   la.launch_err = d_launch_err;
   la.total = (long long)total;
+  la.nq = nq;
+  la.qoff[0] = 0;
+  for (int x = 0; x < MAX_XQ; x++) {
+    la.qoff[x + 1] = x < nq ? la.qoff[x] + qtotal[(size_t)x] : la.qoff[x];
+    la.prefill[x] = qfill[(size_t)x];
+  }
+  if (nq == 1) la.qoff[1] = (long long)total;
+  for (int x = nq + 1; x <= MAX_XQ; x++) la.qoff[x] = la.qoff[nq];
+  if (mode == 0 && la.qoff[nq] != (long long)total)
+    return fail(MD_EINVAL, "work queues hold %lld items, the launch %lld", la.qoff[nq], (long long)total);
   long long prefill = 0;
   for (size_t q = 0; q < R; q++) prefill += (long long)ra[q].g.S * ra[q].nch;
   if (trace_owner && trace_owner->trace_on) {
@@ -1057,19 +1155,13 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
     la.trace = trace_owner->d_trace;
   }
   if (launch_init(la, std::max<long long>(prefill, max_slices), st)) return fail(MD_EHIP, "init failed");
-  int full = 0, nvt = 0;
-  for (size_t q = 0; q < R; q++) {
-    if (ra[q].count || nsample[idx[q]] > 0 || ra[q].fail_at >= 0) full = 1;
-    if (ra[q].thermo_T > 0.0) nvt = 1;
-  }
-  const int grid = grid_size(prec, full, nvt, grid_override);
   if (last_grid) *last_grid = grid;
   if (kernel_seconds && !ls.ev[0]) {
     HIPCHK(hipEventCreate(&ls.ev[0]));
     HIPCHK(hipEventCreate(&ls.ev[1]));
   }
   if (kernel_seconds) HIPCHK(hipEventRecord(ls.ev[0], st));
-  if (launch_persistent(la, prec, full, nvt, grid, st)) return fail(MD_EHIP, "persistent launch failed");
+  if (launch_persistent(la, prec, kind, nvt, grid, st)) return fail(MD_EHIP, "persistent launch failed");
   if (kernel_seconds) HIPCHK(hipEventRecord(ls.ev[1], st));
   HIPCHK(hipStreamSynchronize(st));
   if (kernel_seconds) {
@@ -1085,7 +1177,9 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   uint32_t lerr = 0;
   HIPCHK(hipMemcpy(&lerr, d_launch_err, sizeof(uint32_t), hipMemcpyDeviceToHost));
   if (lerr) {
-    for (size_t r = 0; r < R; r++) status[r] = fail(MD_EWATCHDOG, "a work-queue wait exceeded the watchdog");
+    for (size_t r = 0; r < R; r++)
+      status[r] = (lerr & ERR_BADINPUT) ? fail(MD_EHIP, "a work queue overflowed (internal error)")
+                                        : fail(MD_EWATCHDOG, "a work-queue wait exceeded the watchdog");
     return MD_OK;
   }
   for (size_t r = 0; r < R; r++) status[r] = finish_run(sims[r], ksteps[r], nsample[r], first_j[r]);
@@ -1105,6 +1199,10 @@ extern "C" int md_step(md_sim* s, int64_t nsteps) {
   s->last_launches = 0;
   s->trace.clear();
   const auto t0 = std::chrono::steady_clock::now();
+  if (nsteps > 0) {
+    const int prc = plan_queues(s);
+    if (prc) return prc;
+  }
   int64_t left = nsteps;
   std::vector<md_sim*> one(1, s);
   std::vector<int64_t> ks(1);
@@ -1136,7 +1234,7 @@ static size_t noalloc_launch_bytes(const md_sim* s, int64_t k) {
   launch_samples(s, k, &nsample, &first_j);
   size_t b = round256(sizeof(RunArgs)) + round256(2 * sizeof(long long));
   b += round256((size_t)(k + 1) * sizeof(long long)) + round256((size_t)(k + 1) * sizeof(int));
-  b += 2 * round256(sizeof(unsigned long long)) + round256(sizeof(uint32_t));
+  b += 2 * round256((size_t)MAX_XQ * XQ_STRIDE * sizeof(unsigned long long)) + round256(sizeof(uint32_t));
   b += round256((size_t)std::max<int64_t>(nsample, 1) * g.S * s->nch * 3 * sizeof(double));
   b += round256((s->miglog_on ? (size_t)k * g.S * 2 : 1) * sizeof(uint32_t));
   if (dataflow) {
@@ -1168,6 +1266,10 @@ extern "C" int md_step_noalloc(md_sim* s, int64_t nsteps) {
   s->last_launches = 0;
   s->trace.clear();
   const auto t0 = std::chrono::steady_clock::now();
+  if (nsteps > 0) {
+    const int prc = plan_queues(s);
+    if (prc) return prc;
+  }
   int64_t left = nsteps;
   std::vector<md_sim*> sims(1, s);
   std::vector<int64_t> ks(1);
@@ -1351,6 +1453,9 @@ extern "C" int md_get_stats(md_sim* s, md_stats* out) {
   out->chunks_per_slice = s->nch;
   out->precision = s->prec;
   out->poisoned = s->poisoned ? 1 : 0;
+  out->work_queues = s->nq;
+  static_assert(MAX_XQ + 1 <= 9, "md_stats.queue_first holds MAX_XQ + 1 entries");
+  for (int x = 0; x < 9; x++) out->queue_first[x] = x <= MAX_XQ ? s->xfirst[x] : s->g.S;
   return MD_OK;
 }
 

@@ -19,6 +19,8 @@ constexpr int CELL_BYTES = CELL_DOUBLES * 8 + CELL_CAP * 4;  // 3328
 constexpr int WG = 256;                      // threads per workgroup (4 waves)
 constexpr int WAVES = WG / 64;
 constexpr int BLOCK_CELLS = WAVES;            // cells of one z-column per staged block (one per wave)
+constexpr int MAX_XQ = 8;                    // work queues at most: one per XCD (L2 domain)
+constexpr int XQ_STRIDE = 32;                // queue counters 256 bytes apart
 
 // error word bits
 constexpr uint32_t ERR_NONFINITE = 1u;
@@ -84,11 +86,16 @@ struct RunArgs {
   double* fbuf;                 // thermostat: F(t) per slot of the step's cells [ncell][3][64]
   double* kpart;                // thermostat: [S][nch][2] kinetic energy and atoms of v(t)
   uint32_t* cntK;               // thermostat: per slice, force items completed in this launch
+  // XCD work queues (LaunchArgs::nq > 1): queue x holds the items of slices
+  // [xfirst[x], xfirst[x + 1]) and its first-step force items start at slot q0[x]
+  int xfirst[MAX_XQ + 1];
+  long long q0[MAX_XQ];
 };
 
 struct TraceRec {
   uint32_t k, slice, chunk, phase;
   uint32_t hw_id, launch;
+  uint32_t xcd, queue;
   unsigned long long t_claim, t_ready, t_done;
 };
 
@@ -105,9 +112,18 @@ struct LaunchArgs {
   uint32_t launch_index;
   int mode;                     // 0 dataflow queue, 1 fixed claim order
   unsigned long long* q;        // dataflow: item slots (top bit set once pushed)
-  unsigned long long* q_tail;   // dataflow: next free slot
+  unsigned long long* q_tail;   // dataflow: next free slot of queue x at q_tail[XQ_STRIDE x]
   uint32_t* launch_err;         // dataflow: a queue wait exceeded the watchdog
   long long total;              // items in the launch
+  // Dataflow work queues.  nq = 1: one queue for the device, every item synchronises at
+  // agent scope.  nq > 1: one queue per XCD; queue x occupies slots [qoff[x], qoff[x+1])
+  // of q, holds the items of each run's slices [xfirst[x], xfirst[x+1]) and is served by
+  // the workgroups running on XCD x only, so items whose inputs all come from the same XCD
+  // exchange data through that XCD's L2 (see release_full).  The claim counter of queue x
+  // is ticket[XQ_STRIDE x].
+  int nq;
+  long long qoff[MAX_XQ + 1];
+  long long prefill[MAX_XQ];    // first-step force items of all runs in queue x
 };
 
 // Host-callable launch wrappers (defined in md_device.hip).
@@ -117,8 +133,9 @@ int launch_load_scatter(const DGeom& g, const double* pos, const double* vel, lo
 int launch_sort_cells(const DGeom& g, unsigned char* cells, uint32_t* ncnt, uint32_t* err,
                       void* stream);
 int launch_init(const LaunchArgs& la, long long work, void* stream);
-int persistent_grid(int prec, int full, int nvt, int* blocks_per_cu, int* cus);
-int launch_persistent(const LaunchArgs& la, int prec, int full, int nvt, int grid, void* stream);
+// kind: 0 plain steps, 1 energy-sampled steps, 2 pair counting (see the kernels)
+int persistent_grid(int prec, int kind, int nvt, int* blocks_per_cu, int* cus);
+int launch_persistent(const LaunchArgs& la, int prec, int kind, int nvt, int grid, void* stream);
 int launch_sync(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int first,
                 double* out_pos, double* out_vel, double* out_force, double* epart,
                 uint32_t* err, void* stream);

@@ -20,6 +20,7 @@ MD_FP64, MD_FP32_FORCE = 0, 1
 OPT_ENERGY_EVERY, OPT_CLAIM_ORDER, OPT_ORDER_SEED, OPT_MIGRATION_LOG = 1, 2, 3, 4
 OPT_CHUNK_CELLS, OPT_COUNT_PAIRS, OPT_WATCHDOG_MS, OPT_GRID = 5, 6, 7, 8
 OPT_FAIL_AT_STEP, OPT_MAX_STEPS_PER_LAUNCH, OPT_TRACE, OPT_CELL_CAPACITY = 9, 10, 11, 12
+OPT_XCD_QUEUES = 13
 ORDER_SWEEP, ORDER_PHASED, ORDER_DESCENDING, ORDER_RANDOM, ORDER_DATAFLOW = 0, 1, 2, 3, 4
 SERVER_FAKE_EXECUTOR = 1
 SERVER_MAX_QUEUED = 4096
@@ -38,17 +39,18 @@ class md_stats(C.Structure):
         ("last_step_seconds", C.c_double), ("last_kernel_seconds", C.c_double),
         ("last_launches", C.c_int32), ("persistent_grid", C.c_int32),
         ("chunks_per_slice", C.c_int32), ("precision", C.c_int32), ("poisoned", C.c_int32),
+        ("work_queues", C.c_int32), ("queue_first", C.c_int32 * 9),
     ]
 
 
 class md_trace_rec(C.Structure):
     _fields_ = [("k", C.c_uint32), ("slice", C.c_uint32), ("chunk", C.c_uint32), ("phase", C.c_uint32),
-                ("hw_id", C.c_uint32), ("launch", C.c_uint32),
+                ("hw_id", C.c_uint32), ("launch", C.c_uint32), ("xcd", C.c_uint32), ("queue", C.c_uint32),
                 ("t_claim", C.c_uint64), ("t_ready", C.c_uint64), ("t_done", C.c_uint64)]
 
 
 TRACE_DTYPE = np.dtype([("k", "<u4"), ("slice", "<u4"), ("chunk", "<u4"), ("phase", "<u4"),
-                        ("hw_id", "<u4"), ("launch", "<u4"),
+                        ("hw_id", "<u4"), ("launch", "<u4"), ("xcd", "<u4"), ("queue", "<u4"),
                         ("t_claim", "<u8"), ("t_ready", "<u8"), ("t_done", "<u8")])
 
 

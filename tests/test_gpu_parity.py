@@ -517,3 +517,56 @@ def test_torch_caching_allocator_gives_the_same_trajectory(c0):
         md.set_allocator(None, None)
     for a, b in zip(want, got):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def long_fluid():
+    # 32 slices: at least 3 slices for each of the GPU's XCD work queues
+    box, pos, vel, _ = inputs.homogeneous(32768, 0.8, 1.0, 23, aspect=(4.0, 1.0, 1.0))
+    return inputs.System("long", box, 32, pos, vel)
+
+
+def run_queues(system, prec, xcd_queues):
+    """20 plain steps, then 20 with energy samples (both persistent kernel variants)."""
+    from paper_2507_11289_amd import tracecheck
+
+    with md.Sim(system.box, system.slices, system.rc, system.dt, prec) as sim:
+        sim.set_option(md.OPT_XCD_QUEUES, xcd_queues)
+        sim.set_option(md.OPT_MIGRATION_LOG, 1)
+        sim.set_option(md.OPT_TRACE, 1)
+        sim.load(system.pos, system.vel)
+        sim.step(20)
+        mig_a = sim.migration_log()
+        rec, _ = sim.trace()
+        st = sim.stats()
+        first = list(st.queue_first)[: st.work_queues + 1]
+        sim.set_option(md.OPT_ENERGY_EVERY, 5)
+        sim.step(20)
+        out = {"state": sim.state(), "cells": sim.cells(), "elog": sim.energy_log(),
+               "mig": np.concatenate([mig_a, sim.migration_log()]), "queues": st.work_queues,
+               "first": first, "rec": rec}
+    assert tracecheck.check(rec, system.slices)["violations"] == []
+    return out
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_xcd_queues_are_bitwise_the_single_queue(long_fluid, prec):
+    """One work queue per XCD (items of slices whose neighbours share the XCD synchronise
+    through its L2 only) gives bitwise the results of one device-wide queue; every item
+    ran on the XCD of its queue, and each queue owns a contiguous range of slices."""
+    say(f"[gpu] XCD work queues vs one queue, precision={prec}")
+    one = run_queues(long_fluid, prec, 0)
+    xq = run_queues(long_fluid, prec, 1)
+    assert one["queues"] == 1
+    say(f"    queues {xq['queues']}, ranges {xq['first']}")
+    assert xq["queues"] > 1
+    first = np.array(xq["first"])
+    assert first[0] == 0 and first[-1] == long_fluid.slices and (np.diff(first) >= 3).all()
+    rec = xq["rec"]
+    owner = np.searchsorted(first, rec["slice"], side="right") - 1
+    np.testing.assert_array_equal(rec["queue"], owner)
+    np.testing.assert_array_equal(rec["xcd"], rec["queue"])
+    for a, b in zip(one["state"], xq["state"]):
+        np.testing.assert_array_equal(a, b)
+    for key in ("cells", "elog", "mig"):
+        np.testing.assert_array_equal(one[key], xq[key])

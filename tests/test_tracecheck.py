@@ -18,7 +18,7 @@ def sweep_trace(S=6, K=3, nch=2, ncha=1, nvt=False, launches=1):
             for ph, n in phases:
                 for s in range(S):
                     for c in range(n):
-                        recs.append((k, s, c, ph, 0, L, t, t + 1, t + 10))
+                        recs.append((k, s, c, ph, 0, L, 0, 0, t, t + 1, t + 10))
                         t += 11
     return np.array(recs, dtype=TRACE_DTYPE)
 
