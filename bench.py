@@ -47,12 +47,52 @@ HBM_PEAK = 8000.0      # GB/s
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11289_amd", "csrc", f)
                   for f in ("md_device.hip", "md_host.hip", "md_internal.h")]
 
-# Counter figures of the FP32-force persistent kernel on lj_fluid_4m per atom-step, from
-# rocprofv3 --pmc runs of this file (FETCH_SIZE and WRITE_SIZE scaled by what the same
-# counters read for a plain device copy of known size; SQ_INSTS_VALU_FLOPS_FP32 and the
-# MFMA counters).  They are reported only while the kernel sources have the hash they were
-# taken on (profiles/persistent_f32_lean_lj_fluid_4m.md); otherwise null.
-COUNTERS = None
+# Counter figures of the persistent kernels on lj_fluid_4m per atom-step, from rocprofv3
+# --pmc runs of this file over 100-step launches: FETCH_SIZE and WRITE_SIZE scaled by what
+# the same counters read for a plain device copy of known size (0.50001 and 1.00000);
+# SQ_INSTS_VALU_FLOPS_FP32/FP64 x 64 (the counter gives FLOPs per 64 lanes, read on an FP32
+# multiply of known size); SQ_INSTS_VALU_MFMA_MOPS_F32 x 512.  They are reported only while
+# the kernel sources have the hash they were taken on (profiles/persistent_f32_lean_lj_fluid_4m.md,
+# profiles/persistent_f64_lean_lj_fluid_4m.md); otherwise null.
+COUNTERS = {
+    "source_sha256": "53aa20b526cae24b74336eff2e21d865e4861fb10c49c7f70013a9031a7aac44",
+    "workload": "lj_fluid_4m",
+    "persistent_f32_lean": {
+        "hbm_read_bytes_per_atom_step": 334.9, "hbm_write_bytes_per_atom_step": 63.5,
+        "valu_fp32_flop_per_atom_step": 2272.0, "valu_fp64_flop_per_atom_step": 244.6,
+        "mfma_f32_flop_per_atom_step": 3773.0, "valu_instructions_per_cell_step": 1338.0,
+        "valu_pipe_busy": 0.751, "l2_hit_rate": 0.373, "lds_conflict_cycles_per_lds_cycle": 1.085,
+        "profile": "profiles/persistent_f32_lean_lj_fluid_4m.md"},
+    "persistent_f64_lean": {
+        "hbm_read_bytes_per_atom_step": 307.8, "hbm_write_bytes_per_atom_step": 63.5,
+        "valu_fp32_flop_per_atom_step": 82.5, "valu_fp64_flop_per_atom_step": 4955.0,
+        "mfma_f32_flop_per_atom_step": 3773.0, "valu_instructions_per_cell_step": 2083.0,
+        "valu_pipe_busy": 0.629, "l2_hit_rate": 0.398, "lds_conflict_cycles_per_lds_cycle": 0.264,
+        "profile": "profiles/persistent_f64_lean_lj_fluid_4m.md"},
+}
+
+
+def counter_report(kernel, workload, atom_steps_per_launch, launch_s):
+    """Counter figures of `kernel` scaled to one launch of the timed leg: HBM bytes per
+    launch, GB/s, executed FLOP/s; None when the sources or the workload differ from the
+    profiled ones."""
+    if not COUNTERS or COUNTERS["source_sha256"] != source_sha() or workload != COUNTERS["workload"]:
+        return None
+    c = COUNTERS[kernel]
+    bpas = c["hbm_read_bytes_per_atom_step"] + c["hbm_write_bytes_per_atom_step"]
+    per_launch = bpas * atom_steps_per_launch
+    return {
+        "hbm_bytes_per_launch": per_launch, "hbm_bytes_per_atom_step": bpas,
+        "algorithmic_bytes_per_atom_step": 104.0, "hbm_gbs": per_launch / launch_s / 1e9,
+        "frac_hbm_peak": per_launch / launch_s / 1e9 / HBM_PEAK,
+        "executed_valu_fp32_tflops": c["valu_fp32_flop_per_atom_step"] * atom_steps_per_launch / launch_s / 1e12,
+        "executed_valu_fp64_tflops": c["valu_fp64_flop_per_atom_step"] * atom_steps_per_launch / launch_s / 1e12,
+        "executed_mfma_f32_tflops": c["mfma_f32_flop_per_atom_step"] * atom_steps_per_launch / launch_s / 1e12,
+        "valu_instructions_per_cell_step": c["valu_instructions_per_cell_step"],
+        "valu_pipe_busy": c["valu_pipe_busy"], "l2_hit_rate": c["l2_hit_rate"],
+        "lds_conflict_cycles_per_lds_cycle": c["lds_conflict_cycles_per_lds_cycle"],
+        "profile": c["profile"],
+    }
 
 
 def log(*a):
@@ -367,6 +407,20 @@ def copy_calibration(nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
 
 
+def flop_calibration(n=1 << 28, reps=5):
+    """An elementwise FP32 product of known size (n multiplies per launch), for reading the
+    lane factor of the SQ_INSTS_VALU_FLOPS_FP32 counter."""
+    import torch
+
+    a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a).uniform_()
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        a.mul_(b)
+    torch.cuda.synchronize()
+    print(json.dumps({"fp32_multiplies_per_launch": n, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,6 +439,8 @@ def main():
     ap.add_argument("--fp32-only", action="store_true")
     ap.add_argument("--launch-steps", type=int, default=100,
                     help="steps per persistent launch (warm-up and timed launches alike)")
+    ap.add_argument("--flop-calibration", action="store_true",
+                    help="only run an FP32 multiply of known size (counter calibration)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -404,6 +460,9 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.flop_calibration:
+        flop_calibration()
         return
     stream = torch.cuda.Stream()
     log(f"[bench] generating {args.workload}")
@@ -427,22 +486,9 @@ def main():
     steps_per_launch = args.steps / max(main_leg["launches"], 1)
     atom_steps_per_launch = n * steps_per_launch
     achieved = flop_per_atom_step * atom_steps_per_launch / launch_s / 1e12
-    traffic = None
-    counters = None
-    if COUNTERS and COUNTERS["source_sha256"] == source_sha() and sysm.name == COUNTERS["workload"]:
-        bpas = COUNTERS["hbm_bytes_per_atom_step"]
-        traffic = bpas * atom_steps_per_launch / launch_s / 1e9
-        counters = {
-            "hbm_bytes_per_atom_step": bpas, "algorithmic_bytes_per_atom_step": 104.0,
-            "frac_hbm_peak": traffic / HBM_PEAK,
-            "executed_valu_fp32_tflops": COUNTERS["valu_fp32_flop_per_atom_step"] * atom_steps_per_launch
-            / launch_s / 1e12,
-            "executed_valu_fp64_tflops": COUNTERS["valu_fp64_flop_per_atom_step"] * atom_steps_per_launch
-            / launch_s / 1e12,
-            "executed_mfma_f32_tflops": COUNTERS["mfma_f32_flop_per_atom_step"] * atom_steps_per_launch
-            / launch_s / 1e12,
-            "profile": COUNTERS["profile"],
-        }
+    # HBM bytes per launch of the timed leg (from the counters' bytes per atom-step)
+    counters = counter_report("persistent_f32_lean", sysm.name, atom_steps_per_launch, launch_s)
+    traffic = counters["hbm_bytes_per_launch"] if counters else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -486,7 +532,10 @@ def main():
         a64 = (8.0 * f["C"] + 14.0 * f["P"]) * n * args.steps / f["kernel_s"] / 1e12
         out["fp64"] = {"value": v64, "ms_per_step": 1e3 * f["event_s"] / args.steps,
                        "achieved_tflops": a64, "frac_fp64_peak": a64 / FP64_PEAK,
-                       "kernel": "persistent_f64_lean"}
+                       "kernel": "persistent_f64_lean",
+                       "counters": counter_report("persistent_f64_lean", sysm.name,
+                                                  n * args.steps / max(f["launches"], 1),
+                                                  f["kernel_s"] / max(f["launches"], 1))}
         out["fp32_force_speedup_vs_fp64"] = value / v64
 
     def leg(name, fn):
