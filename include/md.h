@@ -77,6 +77,9 @@ enum md_option {
     MD_OPT_CELL_CAPACITY = 12,  /* atoms a cell may hold, 1..64 (default 64): a load or step that
                                    puts more atoms in a cell fails with MD_ECAPACITY (forces the
                                    capacity guard in tests) */
+    MD_OPT_WAVEFRONT_LEVELS = 14, /* time levels W of MD_ORDER_WAVEFRONT, 1..64 (default 4); md_step
+                                   launches whole multiples of W steps (a shorter remainder runs
+                                   as its own launch) */
     MD_OPT_XCD_QUEUES = 13      /* 1: under MD_ORDER_DATAFLOW, one work queue per XCD of the GPU,
                                    each owning a contiguous range of slices balanced by atoms (and
                                    cells) per slice, so that the items of a slice share one L2 and
@@ -93,8 +96,15 @@ enum md_claim_order {
     MD_ORDER_PHASED = 1,      /* all force/integrate items of a step, then all finalise items */
     MD_ORDER_DESCENDING = 2,  /* the sweep mirrored */
     MD_ORDER_RANDOM = 3,      /* a seeded random order that respects the dependencies */
-    MD_ORDER_DATAFLOW = 4     /* items are queued the moment their inputs are complete and
+    MD_ORDER_DATAFLOW = 4,    /* items are queued the moment their inputs are complete and
                                  taken in queue order (no worker waits on a dependency) */
+    MD_ORDER_WAVEFRONT = 5    /* multi-time-level sweep (the one-GPU analogue of several workers
+                                 per GPU at different time levels, Sec. 3.1 and Eq. (1)): items of
+                                 MD_OPT_WAVEFRONT_LEVELS consecutive steps are dealt as two
+                                 wavefronts running from slice 0 towards slice S/2 in both
+                                 directions, each later step three slices behind the one before,
+                                 so that W time levels are in flight in a window of about 6W
+                                 slices (md_wavefront_table) */
 };
 
 typedef struct md_stats {
@@ -239,6 +249,15 @@ const char *md_last_error(void);
  * integration of step t, phase 1 = finalisation of step t+1.  MD_ORDER_SWEEP follows the
  * stage order of Table 1: after slice k is integrated, slice k-1 is complete.  Host-only. */
 int md_claim_table(int slices, int order, uint64_t seed, uint16_t *out);
+
+/* The claim table of MD_ORDER_WAVEFRONT for `levels` consecutive steps: 2 * slices * levels
+ * entries (j << 16) | (phase << 15) | slice, j = step within the group of levels.  Integrate
+ * (phase 0) of slice i at step j has key 6j + 2d(i) and finalise (phase 1) of slice i for
+ * step j+1 has key 6j + 2 max(d(i-1), d(i), d(i+1)) + 1, with d(i) = min(i, S - i) the
+ * distance from slice 0 on the ring; entries are sorted by key, then phase, then slice.
+ * Because d changes by at most one between neighbours, every entry follows the entries it
+ * depends on.  Host-only.  MD_EINVAL for slices < 3, levels outside 1..64 or NULL. */
+int md_wavefront_table(int slices, int levels, uint32_t *out);
 
 /* Device bytes a served run of this system holds at most (the admission measure): two
  * cell buffers of 3328 B per cell, cell and slice counters, the larger of the load copies

@@ -1521,12 +1521,13 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
           }
           const RunArgs& ra = la.runs[rlo];
           const int local = (int)(rem - la.run_prefix[rlo]);
-          // fixed claim orders: both phases have nch items per slice (nchA == nch)
+          // fixed claim orders: both phases have nch items per slice (nchA == nch); a round
+          // holds wlev steps, the table gives each entry's step within the round
           const int entry = local / ra.nch;
           const unsigned ord = ra.order[entry];
           it.run = rlo;
-          it.k = k;
-          it.phase = (int)(ord >> 15);
+          it.k = k * ra.wlev + (int)(ord >> 16);
+          it.phase = (int)((ord >> 15) & 1u);
           it.slice = (int)(ord & 0x7fffu);
           it.chunk = local - entry * ra.nch;
           it.go = 1;

@@ -254,6 +254,44 @@ extern "C" int md_claim_table(int slices, int order, uint64_t seed, uint16_t* ou
   return MD_OK;
 }
 
+// Multi-time-level sweep (MD_ORDER_WAVEFRONT): the entries of `levels` consecutive steps,
+// (j << 16) | (phase << 15) | slice, sorted by key.  Integrate of slice i at step j has key
+// 6j + 2d(i), finalise of slice i for step j+1 has key 6j + 2 max(d(i-1), d(i), d(i+1)) + 1,
+// d(i) = min(i, S - i).  Finalise keys exceed the keys of the integrates they need, and
+// integrate of step j+1 (key 6j + 6 + 2d(i)) exceeds every finalise it needs (at most
+// 6j + 2(d(i) + 2) + 1, since d changes by at most one between neighbours).
+constexpr int MAX_WAVEFRONT_LEVELS = 64;
+static std::vector<uint32_t> make_wavefront(int S, int levels) {
+  struct E {
+    long key;
+    uint32_t v;
+  };
+  std::vector<E> e;
+  e.reserve((size_t)2 * S * levels);
+  auto d = [S](int i) { i = ((i % S) + S) % S; return std::min(i, S - i); };
+  for (int j = 0; j < levels; j++)
+    for (int i = 0; i < S; i++) {
+      e.push_back({6l * j + 2l * d(i), ((uint32_t)j << 16) | (uint32_t)i});
+      const int m = std::max(d(i - 1), std::max(d(i), d(i + 1)));
+      e.push_back({6l * j + 2l * m + 1, ((uint32_t)j << 16) | (1u << 15) | (uint32_t)i});
+    }
+  std::stable_sort(e.begin(), e.end(), [](const E& a, const E& b) {
+    if (a.key != b.key) return a.key < b.key;
+    return (a.v & 0xffffu) < (b.v & 0xffffu);
+  });
+  std::vector<uint32_t> out(e.size());
+  for (size_t k = 0; k < e.size(); k++) out[k] = e[k].v;
+  return out;
+}
+
+extern "C" int md_wavefront_table(int slices, int levels, uint32_t* out) {
+  if (slices < 3 || slices > 32767 || levels < 1 || levels > MAX_WAVEFRONT_LEVELS || !out)
+    return fail(MD_EINVAL, "bad arguments");
+  std::vector<uint32_t> t = make_wavefront(slices, levels);
+  std::memcpy(out, t.data(), t.size() * sizeof(uint32_t));
+  return MD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // device buffers of one simulation / run
 // ---------------------------------------------------------------------------
@@ -376,7 +414,7 @@ struct SimBuffers {
   unsigned long long* migcum = nullptr;
   unsigned long long* paircnt = nullptr;
   unsigned long long* scount = nullptr;  // atoms per slice (work-queue ranges, md_get_slice_counts)
-  uint16_t* order = nullptr;
+  uint32_t* order = nullptr;  // claim table of one round (up to MAX_WAVEFRONT_LEVELS steps)
   int order_len = 0;
 
   int alloc(const DGeom& g) {
@@ -394,8 +432,8 @@ struct SimBuffers {
     if ((rc = dalloc(&migcum, (size_t)2 * g.S))) return rc;
     if ((rc = dalloc(&paircnt, 2))) return rc;
     if ((rc = dalloc(&scount, (size_t)g.S))) return rc;
-    if ((rc = dalloc(&order, (size_t)2 * g.S))) return rc;
-    order_len = 2 * g.S;
+    if ((rc = dalloc(&order, (size_t)2 * g.S * MAX_WAVEFRONT_LEVELS))) return rc;
+    order_len = 2 * g.S * MAX_WAVEFRONT_LEVELS;
     return MD_OK;
   }
   void release() {
@@ -484,6 +522,8 @@ struct md_sim {
   int order_kind = MD_ORDER_DATAFLOW;
   uint64_t order_seed = 1;
   bool order_dirty = true;
+  int wlev = 4;               // MD_OPT_WAVEFRONT_LEVELS
+  int order_wlev = 0;         // steps per round of the uploaded table
   bool miglog_on = false;
   int64_t chunk_cells = 0;
   bool count_pairs = false;
@@ -643,7 +683,7 @@ extern "C" int md_set_option(md_sim* s, int key, int64_t value) {
       s->every = value;
       return MD_OK;
     case MD_OPT_CLAIM_ORDER:
-      if (value < MD_ORDER_SWEEP || value > MD_ORDER_DATAFLOW) return fail(MD_EINVAL, "unknown claim order");
+      if (value < MD_ORDER_SWEEP || value > MD_ORDER_WAVEFRONT) return fail(MD_EINVAL, "unknown claim order");
       s->order_kind = (int)value;
       s->order_dirty = true;
       return MD_OK;
@@ -679,6 +719,12 @@ extern "C" int md_set_option(md_sim* s, int key, int64_t value) {
     case MD_OPT_CELL_CAPACITY:
       if (value < 1 || value > CELL_CAP) return fail(MD_EINVAL, "cell capacity must be in [1, %d]", CELL_CAP);
       s->g.cap = (int)value;
+      return MD_OK;
+    case MD_OPT_WAVEFRONT_LEVELS:
+      if (value < 1 || value > MAX_WAVEFRONT_LEVELS)
+        return fail(MD_EINVAL, "wavefront levels must be in [1, %d]", MAX_WAVEFRONT_LEVELS);
+      s->wlev = (int)value;
+      s->order_dirty = true;
       return MD_OK;
     case MD_OPT_XCD_QUEUES:
       s->xcd_queues = value != 0;
@@ -838,12 +884,23 @@ static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st
                        int64_t* nsample_out, int64_t* first_j_out, Carve* arena) {
   const DGeom& g = s->g;
   int rc;
-  if (s->order_dirty) {
-    std::vector<uint16_t> ord =
-        make_order(g.S, s->order_kind == MD_ORDER_DATAFLOW ? MD_ORDER_SWEEP : s->order_kind, s->order_seed);
-    HIPCHK(hipMemcpy(s->b.order, ord.data(), ord.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  // claim table of one round: wlev steps of the wavefront (as many as this launch holds),
+  // else one step of a per-step order
+  const int wlev = s->order_kind == MD_ORDER_WAVEFRONT ? (int)std::min<int64_t>(s->wlev, k_steps) : 1;
+  if (s->order_dirty || wlev != s->order_wlev) {
+    std::vector<uint32_t> ord;
+    if (s->order_kind == MD_ORDER_WAVEFRONT) {
+      ord = make_wavefront(g.S, wlev);
+    } else {
+      const std::vector<uint16_t> o =
+          make_order(g.S, s->order_kind == MD_ORDER_DATAFLOW ? MD_ORDER_SWEEP : s->order_kind, s->order_seed);
+      ord.assign(o.begin(), o.end());
+    }
+    HIPCHK(hipMemcpy(s->b.order, ord.data(), ord.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     s->order_dirty = false;
+    s->order_wlev = wlev;
   }
+  if (k_steps % wlev != 0) return fail(MD_EINVAL, "launch of %lld steps is not whole rounds of %d", (long long)k_steps, wlev);
   int64_t nsample = 0, first_j = 0;
   launch_samples(s, k_steps, &nsample, &first_j);
   const size_t ep = (size_t)std::max<int64_t>(nsample, 1) * g.S * s->nch * 3;
@@ -885,6 +942,7 @@ static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st
   ra->err = s->b.err;
   ra->abort = s->b.abort;
   ra->order = s->b.order;
+  ra->wlev = wlev;
   ra->t0 = s->t;
   ra->nsteps = (int)k_steps;
   ra->par0 = s->par;
@@ -1085,11 +1143,17 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
       qtotal[(size_t)x] += ksteps[idx[q]] * nsl * per_slice;
     }
   }
-  std::vector<long long> rb((size_t)nrounds + 1, 0);
-  std::vector<int> act((size_t)nrounds + 1, 0);
+  // tickets are dealt round by round; a round is one step of every active run, or the
+  // wlev steps of the one run of a wavefront launch
+  const int spr = (mode == 1 && R == 1) ? ra[0].wlev : 1;
+  const int64_t nrounds_d = nrounds / spr;
+  if (spr > 1)
+    for (size_t q = 0; q <= R; q++) prefix[q] *= spr;
+  std::vector<long long> rb((size_t)nrounds_d + 1, 0);
+  std::vector<int> act((size_t)nrounds_d + 1, 0);
   size_t a = R;
-  for (int64_t k = 0; k < nrounds; k++) {
-    while (a > 0 && ksteps[idx[a - 1]] <= k) a--;
+  for (int64_t k = 0; k < nrounds_d; k++) {
+    while (a > 0 && ksteps[idx[a - 1]] <= k * spr) a--;
     act[(size_t)k] = (int)a;
     rb[(size_t)k + 1] = rb[(size_t)k] + prefix[a];
   }
@@ -1097,7 +1161,7 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   HIPCHK(hipMemcpy(d_run_prefix, prefix.data(), prefix.size() * sizeof(long long), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(d_round_base, rb.data(), rb.size() * sizeof(long long), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(d_round_active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice));
-  const size_t total = (size_t)rb[(size_t)nrounds];
+  const size_t total = (size_t)rb[(size_t)nrounds_d];
   if (nrounds >= (1 << 19)) return fail(MD_EINVAL, "too many steps in one launch");
   unsigned long long* d_q = nullptr;
   if (mode == 0) {
@@ -1118,7 +1182,7 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   LaunchArgs la{};
   la.runs = d_runs;
   la.nruns = (int)R;
-  la.nrounds = (int)nrounds;
+  la.nrounds = (int)nrounds_d;
   la.round_base = d_round_base;
   la.round_active = d_round_active;
   la.run_prefix = d_run_prefix;
@@ -1209,6 +1273,8 @@ extern "C" int md_step(md_sim* s, int64_t nsteps) {
   std::vector<int> st;
   while (left > 0) {
     ks[0] = std::min(left, s->max_steps_per_launch);
+    // a wavefront launch holds whole rounds of wlev steps; a shorter rest runs alone
+    if (s->order_kind == MD_ORDER_WAVEFRONT && ks[0] >= s->wlev) ks[0] -= ks[0] % s->wlev;
     double ksec = 0;
     int rc = packed_launch(one, ks, *s->ls, s->stream, s->grid_override, s->watchdog_ms, &s->last_grid, st,
                            &ksec, s, (uint32_t)s->last_launches);
@@ -1282,6 +1348,7 @@ extern "C" int md_step_noalloc(md_sim* s, int64_t nsteps) {
       if (noalloc_launch_bytes(s, mid) <= (size_t)MD_NOALLOC_SCRATCH_BYTES) lo = mid;
       else hi = mid - 1;
     }
+    if (s->order_kind == MD_ORDER_WAVEFRONT && lo >= s->wlev) lo -= lo % s->wlev;
     ks[0] = lo;
     Carve arena{base, (size_t)MD_NOALLOC_SCRATCH_BYTES, 0};
     int rc = packed_launch(sims, ks, *s->ls, s->stream, s->grid_override, s->watchdog_ms, &s->last_grid, st,

@@ -69,7 +69,10 @@ struct RunArgs {
   unsigned long long* paircnt;  // [2] candidates, in-range (count mode)
   uint32_t* err;                // error word of this run
   uint32_t* abort;              // set on any error of this run; its waits give up
-  const uint16_t* order;        // per-step claim table, 2*S entries: (phase << 15) | slice
+  const uint32_t* order;        // claim table of one round of wlev steps, 2*S*wlev entries:
+                                // (j << 16) | (phase << 15) | slice, j = step within the round
+  int wlev;                     // steps per round of a fixed claim order (1, or the wavefront's
+                                // time levels)
   long long t0;                 // absolute step at the start of the launch
   int nsteps;                   // steps in this launch
   int par0;                     // parity of the sorted buffer at t0

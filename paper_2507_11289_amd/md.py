@@ -20,8 +20,8 @@ MD_FP64, MD_FP32_FORCE = 0, 1
 OPT_ENERGY_EVERY, OPT_CLAIM_ORDER, OPT_ORDER_SEED, OPT_MIGRATION_LOG = 1, 2, 3, 4
 OPT_CHUNK_CELLS, OPT_COUNT_PAIRS, OPT_WATCHDOG_MS, OPT_GRID = 5, 6, 7, 8
 OPT_FAIL_AT_STEP, OPT_MAX_STEPS_PER_LAUNCH, OPT_TRACE, OPT_CELL_CAPACITY = 9, 10, 11, 12
-OPT_XCD_QUEUES = 13
-ORDER_SWEEP, ORDER_PHASED, ORDER_DESCENDING, ORDER_RANDOM, ORDER_DATAFLOW = 0, 1, 2, 3, 4
+OPT_XCD_QUEUES, OPT_WAVEFRONT_LEVELS = 13, 14
+ORDER_SWEEP, ORDER_PHASED, ORDER_DESCENDING, ORDER_RANDOM, ORDER_DATAFLOW, ORDER_WAVEFRONT = 0, 1, 2, 3, 4, 5
 SERVER_FAKE_EXECUTOR = 1
 SERVER_MAX_QUEUED = 4096
 NOALLOC_SCRATCH_BYTES = 16 << 20
@@ -96,6 +96,7 @@ _SIGS = {
     "md_last_error": ([], C.c_char_p),
     "md_footprint_bytes": ([C.POINTER(C.c_double), C.c_int, C.c_double, C.c_int64], C.c_int64),
     "md_claim_table": ([C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_uint16)], C.c_int),
+    "md_wavefront_table": ([C.c_int, C.c_int, C.POINTER(C.c_uint32)], C.c_int),
     "md_server_create": ([C.c_size_t, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
     "md_server_create_ex": ([C.c_size_t, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
     "md_submit": ([C.c_void_p, C.POINTER(md_run_desc), C.POINTER(C.c_uint64)], C.c_int),
@@ -170,6 +171,14 @@ def md_claim_table(slices: int, order: int, seed: int = 1) -> np.ndarray:
     _check(lib().md_claim_table(int(slices), int(order), int(seed), t.ctypes.data_as(C.POINTER(C.c_uint16))),
            "md_claim_table")
     return np.stack([t >> 15, t & 0x7FFF], axis=1).astype(np.int64)
+
+
+def md_wavefront_table(slices: int, levels: int) -> np.ndarray:
+    """Claim table of MD_ORDER_WAVEFRONT as (step, phase, slice) rows, shape (2*slices*levels, 3)."""
+    t = np.zeros(2 * slices * levels, np.uint32)
+    _check(lib().md_wavefront_table(int(slices), int(levels), t.ctypes.data_as(C.POINTER(C.c_uint32))),
+           "md_wavefront_table")
+    return np.stack([t >> 16, (t >> 15) & 1, t & 0x7FFF], axis=1).astype(np.int64)
 
 
 _allocator_refs = None

@@ -570,3 +570,42 @@ def test_xcd_queues_are_bitwise_the_single_queue(long_fluid, prec):
         np.testing.assert_array_equal(a, b)
     for key in ("cells", "elog", "mig"):
         np.testing.assert_array_equal(one[key], xq[key])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_wavefront_sweep_is_bitwise_the_dataflow_run(long_fluid, prec):
+    """The multi-time-level sweep (W steps dealt as outward wavefronts, each step three
+    slices behind the one before) gives bitwise the dataflow run's state, energies and
+    migrations, with whole rounds of W steps and a shorter rest launch (7 = 3 + 3 + 1)."""
+    from paper_2507_11289_amd import tracecheck
+
+    say(f"[gpu] wavefront sweep, precision={prec}")
+    outs = []
+    for order, levels in ((md.ORDER_DATAFLOW, 0), (md.ORDER_WAVEFRONT, 3), (md.ORDER_WAVEFRONT, 8)):
+        with md.Sim(long_fluid.box, long_fluid.slices, long_fluid.rc, long_fluid.dt, prec) as sim:
+            sim.set_option(md.OPT_CLAIM_ORDER, order)
+            if levels:
+                sim.set_option(md.OPT_WAVEFRONT_LEVELS, levels)
+            sim.set_option(md.OPT_MIGRATION_LOG, 1)
+            sim.set_option(md.OPT_ENERGY_EVERY, 2)
+            sim.set_option(md.OPT_TRACE, 1)
+            sim.load(long_fluid.pos, long_fluid.vel)
+            sim.step(7)
+            rec, _ = sim.trace()
+            launches = sim.stats().last_launches
+            outs.append((sim.state(), sim.energy_log(), sim.migration_log(), sim.cells()))
+        assert tracecheck.check(rec, long_fluid.slices)["violations"] == []
+        if levels == 3:
+            assert launches == 2      # 6 steps in whole rounds, then the 1-step rest
+        if levels:
+            # items of several steps ran at once: a later step's first item started before
+            # an earlier step's last item finished
+            ph0 = rec[(rec["phase"] == 0) & (rec["launch"] == 0)]
+            k = ph0["k"]
+            assert any(ph0["t_ready"][k == j + 1].min() < ph0["t_done"][k == j].max()
+                       for j in range(int(k.max())))
+    for other in outs[1:]:
+        for a, b in zip(outs[0][0], other[0]):
+            np.testing.assert_array_equal(a, b)
+        for a, b in zip(outs[0][1:], other[1:]):
+            np.testing.assert_array_equal(a, b)

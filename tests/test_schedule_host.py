@@ -71,3 +71,60 @@ def test_sweep_order_follows_table_1(N):
     assert integ == list(range(N))
     # the periodic exception: slice 0 is finalised last, right after slice N-1
     assert t[-1] == (1, 0) and t[-2] == (1, N - 1)
+
+
+def valid_wavefront(table, S, W):
+    """Every (step, phase, slice) of W steps once; finalise of slice i (for step j+1) after the
+    integrates of i-1, i, i+1 at step j; integrate of slice i at step j >= 1 after the
+    finalises of i-1, i, i+1 for step j."""
+    seen = set()
+    integ = np.zeros((W, S), bool)
+    fin = np.zeros((W, S), bool)
+    for j, phase, s in table:
+        assert (j, phase, s) not in seen
+        seen.add((j, phase, s))
+        nb = [(s - 1) % S, s, (s + 1) % S]
+        if phase == 0:
+            if j > 0:
+                assert all(fin[j - 1, t] for t in nb)
+            integ[j, s] = True
+        else:
+            assert all(integ[j, t] for t in nb)
+            fin[j, s] = True
+    assert len(seen) == 2 * S * W
+
+
+@pytest.mark.parametrize("S", [3, 4, 5, 17, 64, 512])
+@pytest.mark.parametrize("W", [1, 2, 3, 8, 64])
+def test_wavefront_tables_respect_the_dependencies(S, W):
+    valid_wavefront(md.md_wavefront_table(S, W), S, W)
+
+
+def test_wavefront_keeps_levels_in_flight_in_a_window():
+    """S = 64, W = 8: the sweep starts every step at slice 0 and moves outward in both
+    directions; a later step starts before an earlier one has reached the far side, and
+    over the middle of the table the entries of any 64 consecutive table positions touch
+    several steps but only a window of slices."""
+    S, W = 64, 8
+    t = md.md_wavefront_table(S, W)
+    first = {j: min(i for i, e in enumerate(t) if e[0] == j) for j in range(W)}
+    last = {j: max(i for i, e in enumerate(t) if e[0] == j) for j in range(W)}
+    for j in range(1, W):
+        assert first[j] < last[j - 1]            # levels overlap
+    mid = t[len(t) // 3: 2 * len(t) // 3]
+    for k in range(0, len(mid) - 64, 16):
+        w = mid[k:k + 64]
+        assert len(set(w[:, 0])) >= 2
+        d = np.minimum(w[:, 2], S - w[:, 2])     # distance from slice 0
+        assert d.max() - d.min() <= 3 * W + 4
+    # the first entries: integrate of slice 0, then its neighbours
+    assert tuple(t[0]) == (0, 0, 0)
+
+
+def test_wavefront_table_rejects_bad_arguments():
+    with pytest.raises(md.MDError):
+        md.md_wavefront_table(2, 4)
+    with pytest.raises(md.MDError):
+        md.md_wavefront_table(64, 0)
+    with pytest.raises(md.MDError):
+        md.md_wavefront_table(64, 65)
