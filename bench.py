@@ -302,6 +302,7 @@ def serve_leg(reqs, systems, budget_bytes=96 << 30, max_runs=64, label=""):
     sv = md.Server(budget_bytes, max_runs)
     tickets = {}
     drifts = []
+    waits, runs = [], []  # server clock: admission wait and resident time of each run
     rejected = 0
     t_origin = time.perf_counter()
     pending = set()
@@ -327,9 +328,12 @@ def serve_leg(reqs, systems, budget_bytes=96 << 30, max_runs=64, label=""):
                 results[j] = (rc, time.perf_counter() - t_origin)
                 if rc == md.MD_OK:
                     drifts.append(r.drift_per_atom_step)
+                    waits.append(r.t_admit - r.t_submit)
+                    runs.append(r.t_done - r.t_admit)
         time.sleep(0.0005)
     t_end = time.perf_counter() - t_origin
     stats = sv.stats()
+    thread_s = sv.times()
     sv.close()
     ok = [j for j, (rc, _) in results.items() if rc == md.MD_OK]
     lat = np.array([results[j][1] - reqs[j].arrival for j in ok])
@@ -343,7 +347,11 @@ def serve_leg(reqs, systems, budget_bytes=96 << 30, max_runs=64, label=""):
         "offered_atom_steps_per_s": sum(r.n * r.steps for r in reqs) / max(reqs[-1].arrival, 1e-9),
         "median_drift_per_atom_step": float(np.median(drifts)) if drifts else None,
         "max_abs_drift_per_atom_step": float(np.max(np.abs(drifts))) if drifts else None,
-        "launches": stats["launches"], "wall_s": t_end,
+        "launches": stats["launches"], "wall_s": t_end, "server_thread_s": thread_s,
+        "p50_admission_wait_s": float(np.percentile(waits, 50)) if waits else None,
+        "p99_admission_wait_s": float(np.percentile(waits, 99)) if waits else None,
+        "p50_resident_s": float(np.percentile(runs, 50)) if runs else None,
+        "p99_resident_s": float(np.percentile(runs, 99)) if runs else None,
     }
 
 

@@ -335,6 +335,10 @@ int md_poll(md_server *sv, uint64_t ticket, md_result *out);
 int md_fetch_state(md_server *sv, uint64_t ticket, double *pos, double *vel);
 int md_server_stats(md_server *sv, int64_t *queued, int64_t *running, int64_t *done,
                     int64_t *bytes_in_use, int64_t *launches);
+/* Seconds the server's thread has spent admitting runs (device set-up, load, energy at
+ * t = 0), in packed launches (set-up, kernels, per-run bookkeeping), completing runs (energy
+ * at t = steps, final state, release) and waiting for work.  NULL pointers are skipped. */
+int md_server_times(md_server *sv, double *admit_s, double *launch_s, double *finish_s, double *idle_s);
 int md_server_destroy(md_server *sv);
 
 #ifdef __cplusplus

@@ -1636,7 +1636,11 @@ __global__ void init_launch_kernel(LaunchArgs la) {
   if (i == 0 && la.launch_err) *la.launch_err = 0u;
   for (int r = 0; r < la.nruns; r++) {
     const RunArgs& ra = la.runs[r];
-    if (i == 0) *ra.abort = 0u;
+    if (i == 0) {
+      *ra.abort = 0u;
+      *ra.err = 0u;
+      ra.paircnt[0] = ra.paircnt[1] = 0ull;
+    }
     for (long long s = i; s < ra.g.S; s += stride) {
       ra.cntA[s] = la.mode == 0 ? 0u : (uint32_t)ra.nchA;
       ra.cntF[s] = 0u;
@@ -1652,6 +1656,11 @@ __global__ void init_launch_kernel(LaunchArgs la) {
       }
     }
   }
+}
+
+// After a launch: every run's error word into one array (one copy for the host).
+__global__ void gather_errors_kernel(const RunArgs* runs, int nruns, uint32_t* out) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nruns; r += gridDim.x * blockDim.x) out[r] = *runs[r].err;
 }
 
 // ---------------------------------------------------------------------------
@@ -1833,6 +1842,12 @@ int persistent_grid(int prec, int kind, int nvt, int* blocks_per_cu, int* cus) {
   *blocks_per_cu = nb;
   *cus = prop.multiProcessorCount;
   return 0;
+}
+
+int launch_gather_errors(const RunArgs* runs, int nruns, uint32_t* out, void* stream) {
+  if (nruns <= 0) return 0;
+  hipLaunchKernelGGL(gather_errors_kernel, dim3(grid_for(nruns, 256)), dim3(256), 0, S_(stream), runs, nruns, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_persistent(const LaunchArgs& la, int prec, int kind, int nvt, int grid, void* stream) {

@@ -456,6 +456,7 @@ struct SimBuffers {
 
 struct LaunchScratch {
   RunArgs* d_runs = nullptr;
+  uint32_t* d_errs = nullptr;  // error word of every run after a launch
   size_t runs_cap = 0;
   long long* d_round_base = nullptr;
   int* d_round_active = nullptr;
@@ -476,7 +477,9 @@ struct LaunchScratch {
     if (nruns > runs_cap) {
       dfree(d_runs);
       dfree(d_run_prefix);
-      if ((rc = dalloc(&d_runs, nruns)) || (rc = dalloc(&d_run_prefix, nruns + 1))) return rc;
+      dfree(d_errs);
+      if ((rc = dalloc(&d_runs, nruns)) || (rc = dalloc(&d_run_prefix, nruns + 1)) || (rc = dalloc(&d_errs, nruns)))
+        return rc;
       runs_cap = nruns;
     }
     if (nrounds + 1 > round_cap) {
@@ -489,6 +492,7 @@ struct LaunchScratch {
   }
   void release() {
     dfree(d_runs);
+    dfree(d_errs);
     dfree(d_round_base);
     dfree(d_round_active);
     dfree(d_run_prefix);
@@ -924,8 +928,7 @@ static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st
     s->cur_miglog = s->d_miglog;
   }
   if (s->miglog_on && launch_clear_u32(s->cur_miglog, (long long)ml, 0u, st)) return fail(MD_EHIP, "clear failed");
-  if (launch_clear_u32(reinterpret_cast<uint32_t*>(s->b.paircnt), 4, 0u, st)) return fail(MD_EHIP, "clear failed");
-  if (launch_clear_u32(s->b.err, 1, 0u, st)) return fail(MD_EHIP, "clear failed");
+  // the launch's init kernel clears the error word and the pair counters
   std::memset(ra, 0, sizeof(*ra));
   ra->g = g;
   for (int p = 0; p < 2; p++) {
@@ -977,11 +980,10 @@ static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st
   return MD_OK;
 }
 
-// After a launch: error word, energy samples, migration log, counters, step.
-static int finish_run(md_sim* s, int64_t k_steps, int64_t nsample, int64_t first_j) {
+// After a launch: error word w (gathered for all runs of the launch), energy samples,
+// migration log, counters, step.
+static int finish_run(md_sim* s, uint32_t w, int64_t k_steps, int64_t nsample, int64_t first_j) {
   const DGeom& g = s->g;
-  uint32_t w = 0;
-  HIPCHK(hipMemcpy(&w, s->b.err, sizeof(uint32_t), hipMemcpyDeviceToHost));
   if (w) return fail(err_status(w), "step at t=%lld: %s", (long long)s->t, err_text(w));
   if (nsample > 0) {
     std::vector<double> part((size_t)nsample * g.S * s->nch * 3);
@@ -1078,7 +1080,7 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   long long *d_run_prefix, *d_round_base;
   int* d_round_active;
   unsigned long long *d_ticket, *d_q_tail;
-  uint32_t* d_launch_err;
+  uint32_t *d_launch_err, *d_errs;
   int rc;
   if (arena) {
     d_runs = arena->take<RunArgs>(R);
@@ -1088,7 +1090,9 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
     d_ticket = arena->take<unsigned long long>((size_t)MAX_XQ * XQ_STRIDE);
     d_q_tail = arena->take<unsigned long long>((size_t)MAX_XQ * XQ_STRIDE);
     d_launch_err = arena->take<uint32_t>(1);
-    if (!d_runs || !d_run_prefix || !d_round_base || !d_round_active || !d_ticket || !d_q_tail || !d_launch_err)
+    d_errs = arena->take<uint32_t>(R);
+    if (!d_runs || !d_run_prefix || !d_round_base || !d_round_active || !d_ticket || !d_q_tail || !d_launch_err ||
+        !d_errs)
       return fail(MD_EINVAL, "launch scratch exhausted");
   } else {
     if ((rc = ls.reserve(R, (size_t)nrounds))) return rc;
@@ -1099,6 +1103,7 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
     d_ticket = ls.d_ticket;
     d_q_tail = ls.d_q_tail;
     d_launch_err = ls.d_launch_err;
+    d_errs = ls.d_errs;
   }
   std::vector<RunArgs> ra(R);
   std::vector<int64_t> nsample(R), first_j(R);
@@ -1246,7 +1251,16 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
                                         : fail(MD_EWATCHDOG, "a work-queue wait exceeded the watchdog");
     return MD_OK;
   }
-  for (size_t r = 0; r < R; r++) status[r] = finish_run(sims[r], ksteps[r], nsample[r], first_j[r]);
+  // every run's error word with one copy (ra and d_runs are in sorted order idx)
+  // (the launch stream is non-blocking: the copy goes on it, then the stream is waited for)
+  if (launch_gather_errors(d_runs, (int)R, d_errs, st)) return fail(MD_EHIP, "error gather failed");
+  std::vector<uint32_t> errs(R, 0u);
+  HIPCHK(hipMemcpyAsync(errs.data(), d_errs, R * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (size_t q = 0; q < R; q++) {
+    const size_t r = idx[q];
+    status[r] = finish_run(sims[r], errs[q], ksteps[r], nsample[r], first_j[r]);
+  }
   return MD_OK;
 }
 
@@ -1300,7 +1314,7 @@ static size_t noalloc_launch_bytes(const md_sim* s, int64_t k) {
   launch_samples(s, k, &nsample, &first_j);
   size_t b = round256(sizeof(RunArgs)) + round256(2 * sizeof(long long));
   b += round256((size_t)(k + 1) * sizeof(long long)) + round256((size_t)(k + 1) * sizeof(int));
-  b += 2 * round256((size_t)MAX_XQ * XQ_STRIDE * sizeof(unsigned long long)) + round256(sizeof(uint32_t));
+  b += 2 * round256((size_t)MAX_XQ * XQ_STRIDE * sizeof(unsigned long long)) + 2 * round256(sizeof(uint32_t));
   b += round256((size_t)std::max<int64_t>(nsample, 1) * g.S * s->nch * 3 * sizeof(double));
   b += round256((s->miglog_on ? (size_t)k * g.S * 2 : 1) * sizeof(uint32_t));
   if (dataflow) {
@@ -1576,6 +1590,9 @@ struct md_server {
   std::vector<std::shared_ptr<ServedRun>> running;
   std::map<uint64_t, std::shared_ptr<ServedRun>> runs;
   int64_t in_use = 0, launches = 0, ndone = 0;
+  // seconds the server thread spent admitting runs, in packed launches, completing runs
+  // (read-back and release) and waiting for work
+  double t_admit = 0, t_launch = 0, t_finish = 0, t_idle = 0;
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread th;
@@ -1613,13 +1630,18 @@ static int admit_served(md_server* sv, ServedRun& r) {
   if ((rc = md_set_option(s, MD_OPT_CHUNK_CELLS, SERVED_CHUNK_CELLS))) return rc;
   if ((rc = md_set_stream(s, sv->stream))) return rc;
   if ((rc = md_load(s, r.d.n, r.pos.data(), r.vel.data()))) return rc;
+  // energy samples every energy_every steps are taken inside the packed launches (the
+  // energy-sampling kernel variant), t = 0 among them; t = steps by the read-back at the end
+  if (r.d.energy_every > 0 && (rc = md_set_option(s, MD_OPT_ENERGY_EVERY, r.d.energy_every))) return rc;
   double U, K, W;
   if ((rc = md_energy_virial(s, &U, &K, &W))) return rc;
   r.res.U0 = U;
   r.res.K0 = K;
   r.res.W0 = W;
-  r.sample_t.push_back(0.0);
-  r.sample_e.push_back((U + K) / (double)std::max<int64_t>(r.d.n, 1));
+  if (r.d.energy_every <= 0) {
+    r.sample_t.push_back(0.0);
+    r.sample_e.push_back((U + K) / (double)std::max<int64_t>(r.d.n, 1));
+  }
   std::vector<double>().swap(r.pos);
   std::vector<double>().swap(r.vel);
   return MD_OK;
@@ -1639,6 +1661,10 @@ static int complete_served(md_server* sv, ServedRun& r) {
   r.res.W1 = W;
   std::vector<double> ts = r.sample_t, es = r.sample_e;
   const double n = (double)std::max<int64_t>(r.d.n, 1);
+  for (size_t j = 0; j + 3 < s->elog.size(); j += 4) {  // in-launch samples: (t, U, K, W)
+    ts.push_back(s->elog[j]);
+    es.push_back((s->elog[j + 1] + s->elog[j + 2]) / n);
+  }
   ts.push_back((double)r.d.steps);
   es.push_back((U + K) / n);
   r.res.drift_per_atom_step = drift_slope(ts, es);
@@ -1654,8 +1680,13 @@ static void server_loop(md_server* sv) {
   const bool fake = (sv->flags & MD_SERVER_FAKE_EXECUTOR) != 0;
   if (!fake) (void)hipSetDevice(sv->device);
   std::vector<int64_t> done_steps;
+  auto clock = [] { return std::chrono::steady_clock::now(); };
+  auto secs = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+    return std::chrono::duration<double>(b - a).count();
+  };
   while (true) {
     std::vector<std::shared_ptr<ServedRun>> admit;
+    const auto t_wait = clock();
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       while (true) {
@@ -1675,9 +1706,16 @@ static void server_loop(md_server* sv) {
       }
       for (auto& r : admit) sv->running.push_back(r);
     }
+    const auto t_adm = clock();
     for (auto& r : admit) {
       int rc = admit_served(sv, *r);
       if (rc) finish_served(sv, r, rc);
+    }
+    {
+      const auto t_end = clock();
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->t_idle += secs(t_wait, t_adm);
+      sv->t_admit += secs(t_adm, t_end);
     }
     std::vector<std::shared_ptr<ServedRun>> cur;
     {
@@ -1696,10 +1734,7 @@ static void server_loop(md_server* sv) {
         const int64_t left = r->d.steps - t;
         if (left <= 0) continue;
         const int64_t q = sv->quantum > 0 ? sv->quantum : SERVED_QUANTUM;
-        int64_t k = std::min(left, q);
-        // launches end at the run's energy-sampling steps, which are then taken by a
-        // read-back pass: every launch runs the plain kernel variant
-        if (r->d.energy_every > 0) k = std::min(k, r->d.energy_every - t % r->d.energy_every);
+        const int64_t k = std::min(left, q);
         grp.push_back(r);
         sims.push_back(r->sim);
         ks.push_back(k);
@@ -1707,6 +1742,7 @@ static void server_loop(md_server* sv) {
       if (grp.empty()) continue;
       std::vector<int> st(grp.size(), MD_OK);
       int rc = MD_OK;
+      const auto t_l0 = clock();
       if (fake) {
         int64_t work = 0;
         for (size_t i = 0; i < grp.size(); i++) {
@@ -1717,9 +1753,11 @@ static void server_loop(md_server* sv) {
       } else {
         rc = packed_launch(sims, ks, sv->ls, sv->stream, 0, 20000, nullptr, st);
       }
+      const auto t_l1 = clock();
       {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->launches++;
+        sv->t_launch += secs(t_l0, t_l1);
       }
       for (size_t i = 0; i < grp.size(); i++) {
         const int s = rc ? rc : st[i];
@@ -1728,18 +1766,12 @@ static void server_loop(md_server* sv) {
           continue;
         }
         const int64_t t = fake ? grp[i]->res.steps_done : grp[i]->sim->t;
-        if (t >= grp[i]->d.steps) {
-          finish_served(sv, grp[i], complete_served(sv, *grp[i]));
-        } else if (!fake && grp[i]->d.energy_every > 0 && t % grp[i]->d.energy_every == 0) {
-          double U, K, W;
-          const int e = md_energy_virial(grp[i]->sim, &U, &K, &W);
-          if (e) {
-            finish_served(sv, grp[i], e);
-            continue;
-          }
-          grp[i]->sample_t.push_back((double)t);
-          grp[i]->sample_e.push_back((U + K) / (double)std::max<int64_t>(grp[i]->d.n, 1));
-        }
+        if (t >= grp[i]->d.steps) finish_served(sv, grp[i], complete_served(sv, *grp[i]));
+      }
+      {
+        const auto t_f = clock();
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->t_finish += secs(t_l1, t_f);
       }
     }
   }
@@ -1841,6 +1873,17 @@ extern "C" int md_server_stats(md_server* sv, int64_t* queued, int64_t* running,
   if (done) *done = sv->ndone;
   if (bytes_in_use) *bytes_in_use = sv->in_use;
   if (launches) *launches = sv->launches;
+  return MD_OK;
+}
+
+extern "C" int md_server_times(md_server* sv, double* admit_s, double* launch_s, double* finish_s,
+                               double* idle_s) {
+  if (!sv) return fail(MD_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (admit_s) *admit_s = sv->t_admit;
+  if (launch_s) *launch_s = sv->t_launch;
+  if (finish_s) *finish_s = sv->t_finish;
+  if (idle_s) *idle_s = sv->t_idle;
   return MD_OK;
 }
 

@@ -136,6 +136,7 @@ int launch_load_scatter(const DGeom& g, const double* pos, const double* vel, lo
 int launch_sort_cells(const DGeom& g, unsigned char* cells, uint32_t* ncnt, uint32_t* err,
                       void* stream);
 int launch_init(const LaunchArgs& la, long long work, void* stream);
+int launch_gather_errors(const RunArgs* runs, int nruns, uint32_t* out, void* stream);
 // kind: 0 plain steps, 1 energy-sampled steps, 2 pair counting (see the kernels)
 int persistent_grid(int prec, int kind, int nvt, int* blocks_per_cu, int* cus);
 int launch_persistent(const LaunchArgs& la, int prec, int kind, int nvt, int grid, void* stream);

@@ -103,6 +103,7 @@ _SIGS = {
     "md_poll": ([C.c_void_p, C.c_uint64, C.POINTER(md_result)], C.c_int),
     "md_fetch_state": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "md_server_stats": ([C.c_void_p] + [C.POINTER(C.c_int64)] * 5, C.c_int),
+    "md_server_times": ([C.c_void_p] + [C.POINTER(C.c_double)] * 4, C.c_int),
     "md_server_destroy": ([C.c_void_p], C.c_int),
     "md_set_allocator": ([ALLOC_FN, FREE_FN, C.c_void_p], C.c_int),
 }
@@ -360,6 +361,12 @@ class Server:
         vel = np.zeros((n, 3))
         _check(lib().md_fetch_state(self._h, C.c_uint64(ticket), _dp(pos), _dp(vel)), "md_fetch_state")
         return pos, vel
+
+    def times(self):
+        """Seconds the server thread spent admitting, launching, completing and idle."""
+        v = [C.c_double() for _ in range(4)]
+        _check(lib().md_server_times(self._h, *[C.byref(x) for x in v]), "md_server_times")
+        return dict(zip(("admit_s", "launch_s", "finish_s", "idle_s"), [x.value for x in v]))
 
     def stats(self):
         v = [C.c_int64() for _ in range(5)]
