@@ -262,8 +262,9 @@ int md_wavefront_table(int slices, int levels, uint32_t *out);
 /* Device bytes a served run of this system holds at most (the admission measure): two
  * cell buffers of 3328 B per cell, cell and slice counters, the larger of the load copies
  * and the read-back outputs (72 B per atom), the read-back energy partials, and the launch
- * scratch of one 64-step packed launch with 32 cells per work item (work queue, energy
- * partials, migration log).  -1 for an invalid geometry. */
+ * scratch of one 64-step packed launch with the served work items, a quarter of a slice
+ * of 32 to 64 cells each (work queue, energy partials, migration log).  -1 for an invalid
+ * geometry. */
 int64_t md_footprint_bytes(const double box[3], int slices, double rc, int64_t n);
 
 /* Device memory allocator used for every later device allocation of the library (NULL,

@@ -150,7 +150,13 @@ static int make_geom(const double box[3], int slices, double rc, double dt, int 
 constexpr int64_t FINALISE_MERGE = 4;
 // Served runs: cells per work item (short items keep each step's critical path short)
 // and steps per packed launch when the server is given no quantum.
-constexpr int64_t SERVED_CHUNK_CELLS = 32;
+constexpr int64_t SERVED_CHUNK_MIN = 32, SERVED_CHUNK_MAX = 64;
+// Cells per work item of a served run: a quarter of a slice, within [32, 64] cells: small
+// runs keep four items per slice (a short critical path per step), large runs take items
+// of 64 cells (fewer, so less per-item overhead).
+static int64_t served_chunk_cells(const DGeom& g) {
+  return std::min<int64_t>(SERVED_CHUNK_MAX, std::max<int64_t>(SERVED_CHUNK_MIN, g.cps / 4));
+}
 constexpr int64_t SERVED_QUANTUM = 64;
 
 static int64_t finalise_items(int64_t nch) {
@@ -182,9 +188,9 @@ static int64_t footprint(const DGeom& g, int64_t n, int64_t nch, int64_t launch_
 
 static int auto_chunks(const DGeom& g, int64_t chunk_cells, int64_t n_atoms);
 
-// Footprint of a served run: SERVED_CHUNK_CELLS cells per item, `quantum` steps per launch.
+// Footprint of a served run: served_chunk_cells per item, `quantum` steps per launch.
 static int64_t served_footprint(const DGeom& g, int64_t n, int64_t quantum) {
-  return footprint(g, n, auto_chunks(g, SERVED_CHUNK_CELLS, n), quantum > 0 ? quantum : SERVED_QUANTUM, false);
+  return footprint(g, n, auto_chunks(g, served_chunk_cells(g), n), quantum > 0 ? quantum : SERVED_QUANTUM, false);
 }
 
 extern "C" int64_t md_footprint_bytes(const double box[3], int slices, double rc, int64_t n) {
@@ -1627,7 +1633,7 @@ static int admit_served(md_server* sv, ServedRun& r) {
   if (rc) return rc;
   r.sim = s;
   // served runs are small: short work items keep each step's critical path short
-  if ((rc = md_set_option(s, MD_OPT_CHUNK_CELLS, SERVED_CHUNK_CELLS))) return rc;
+  if ((rc = md_set_option(s, MD_OPT_CHUNK_CELLS, served_chunk_cells(s->g)))) return rc;
   if ((rc = md_set_stream(s, sv->stream))) return rc;
   if ((rc = md_load(s, r.d.n, r.pos.data(), r.vel.data()))) return rc;
   // energy samples every energy_every steps are taken inside the packed launches (the
