@@ -153,14 +153,20 @@ def force_errors(F, ids, oracle_out):
     return {"max": float(e.max()), "median": float(np.median(e)), "atoms": int(len(ids))}
 
 
-def timed_leg(sysm, prec, steps, warmup, stream, launch_steps):
+def timed_leg(sysm, prec, steps, warmup, stream, launch_steps, schedule=None):
     """Warm-up, then exactly `steps` steps in one md_step call bracketed by syncs.
-    Every persistent launch (warm-up and timed) covers at most `launch_steps` steps."""
+    Every persistent launch (warm-up and timed) covers at most `launch_steps` steps.
+    `schedule`: optional (claim order, wavefront levels, XCD queues) for scheduler studies."""
     import torch
 
     sim = md.Sim(sysm.box, sysm.slices, sysm.rc, sysm.dt, prec)
     sim.set_stream(stream.cuda_stream)
     sim.set_option(md.OPT_MAX_STEPS_PER_LAUNCH, launch_steps)
+    if schedule is not None:
+        order, levels, xcd = schedule
+        sim.set_option(md.OPT_CLAIM_ORDER, order)
+        sim.set_option(md.OPT_WAVEFRONT_LEVELS, levels)
+        sim.set_option(md.OPT_XCD_QUEUES, xcd)
     sim.load(sysm.pos, sysm.vel)
     if warmup:
         sim.step(warmup)
@@ -447,6 +453,10 @@ def main():
     ap.add_argument("--fp32-only", action="store_true")
     ap.add_argument("--launch-steps", type=int, default=100,
                     help="steps per persistent launch (warm-up and timed launches alike)")
+    ap.add_argument("--claim-order", choices=["dataflow", "wavefront"], default="dataflow",
+                    help="scheduler of the timed legs (scheduler studies; the headline uses dataflow)")
+    ap.add_argument("--wavefront-levels", type=int, default=4, help="time levels of --claim-order wavefront")
+    ap.add_argument("--xcd-queues", action="store_true", help="one work queue per XCD in the timed legs")
     ap.add_argument("--flop-calibration", action="store_true",
                     help="only run an FP32 multiply of known size (counter calibration)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -478,12 +488,16 @@ def main():
     n = sysm.n
     log(f"[bench] n={n} box={sysm.box} slices={sysm.slices}")
 
+    schedule = None
+    if args.claim_order != "dataflow" or args.xcd_queues:
+        schedule = (md.ORDER_WAVEFRONT if args.claim_order == "wavefront" else md.ORDER_DATAFLOW,
+                    args.wavefront_levels, 1 if args.xcd_queues else 0)
     legs = {}
     for name, prec in (("fp32_force", md.MD_FP32_FORCE), ("fp64", md.MD_FP64)):
         if args.fp32_only and prec == md.MD_FP64:
             continue
         log(f"[bench] timed leg {name}: warmup {args.warmup}, steps {args.steps}")
-        legs[name] = timed_leg(sysm, prec, args.steps, args.warmup, stream, args.launch_steps)
+        legs[name] = timed_leg(sysm, prec, args.steps, args.warmup, stream, args.launch_steps, schedule)
         log(f"[bench]   {legs[name]}")
 
     main_leg = legs["fp32_force"]
@@ -511,6 +525,8 @@ def main():
         "dtype": "f32 pair forces / f64 state, integrator and sums",
         "data": "synthetic",
         "config": {"workload": sysm.name, "n_atoms": n, "box": list(sysm.box),
+                   "schedule": {"claim_order": args.claim_order, "wavefront_levels": args.wavefront_levels
+                                if args.claim_order == "wavefront" else None, "xcd_queues": args.xcd_queues},
                    "slices": sysm.slices, "rc": sysm.rc, "dt": sysm.dt,
                    "rho": sysm.meta.get("rho"), "T": sysm.meta.get("T"), "precision": "fp32_force",
                    "steps_per_launch": steps_per_launch},
