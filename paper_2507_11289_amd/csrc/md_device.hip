@@ -308,12 +308,15 @@ __device__ __forceinline__ void pair64(const DGeom& g, double xi, double yi, dou
 //   stage_issue: every wave loads the atom counts of the block's cells (lane m: staged
 //     cell m) -- issued one block ahead, so they arrive while the previous block is
 //     integrated;
-//   stage_commit: prefix of the counts, capacity check, header; then every thread takes
-//     up to SROUNDS entries of the compact staged list (entries tid, tid + WG, ...),
-//     finds their cell by a binary search over the prefix, and loads all of them at
-//     once (one memory round trip for the whole block), then writes them into LDS.
+//   stage_commit: prefix of the counts, capacity check, header; then each quarter wave
+//     (16 lanes) takes whole staged cells, one atom slot per lane: cell
+//     16 i + 4 w + quarter of wave w for i < SROUNDS, all of them loaded at once (one
+//     memory round trip for the whole block), then written into LDS at the cell's
+//     place in the compact staged list.  Atoms past the 16th of a cell follow in a
+//     second, rarely needed pass.
 // ---------------------------------------------------------------------------
-constexpr int SROUNDS = 4;  // staged entries per thread and memory round trip
+constexpr int SROUNDS = (BCELLS + 15) / 16;  // staged cells per quarter wave
+static_assert(16 * SROUNDS <= 64, "a staged cell index must name a lane of the wave");
 
 // threadIdx.x behind an empty asm: index arithmetic derived from it stays where it is
 // used instead of being hoisted out of the block loop and held in registers through the
@@ -376,10 +379,8 @@ __device__ __forceinline__ float rel32(double x, int s, double L, double o) {
 // wrap: some staged cell of the block is a periodic image (its coordinates are shifted
 // by a box length); without it every shift is 0.
 template <int PREC>
-__device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, BlockLDS<PREC>& L, int m,
-                                          int p, double x, double y, double z, bool wrap) {
-  double o[3];
-  block_origin(g, R.gx, R.gy, R.z0, o);
+__device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, BlockLDS<PREC>& L, const double o[3],
+                                          int m, int p, double x, double y, double z, bool wrap) {
   if constexpr (PREC == 1) {
     float qx, qy, qz;
     if (!wrap) {
@@ -467,44 +468,75 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
   }
   const bool wrap = R.gx == 0 || R.gx == g.G[0] - 1 || R.gy == 0 || R.gy == g.G[1] - 1 || R.z0 == 0 ||
                     R.z0 + nb >= g.G[2];
+  // staged cell of round 0 (round i: m0 + 16 i), i.e. 4 w + quarter; recomputed here so
+  // that the per-round indices are not hoisted out of the block loop and held in registers
   const int tid = opaque_tid();
-  for (int base = 0; base < stot; base += WG * SROUNDS) {
-    int mm[SROUNDS];
-    double x[SROUNDS], y[SROUNDS], z[SROUNDS];
-    // raised wave priority while the list loads are found and issued: the SIMD's other
-    // waves are mostly in VALU-heavy pair loops, and an early issue lets the memory round
-    // trip overlap their work
-    __builtin_amdgcn_s_setprio(2);
+  const int m0 = tid >> 4, j = tid & 15;
+  int pi[SROUNDS];  // staged entry of the lane's slot, or -1
+  int ex[SROUNDS];  // the cell's atoms past its 16th (0 if none, or if not staged)
+  double x[SROUNDS], y[SROUNDS], z[SROUNDS];
+  // raised wave priority while the loads are found and issued: the SIMD's other waves are
+  // mostly in VALU-heavy pair loops, and an early issue lets the memory round trip overlap
+  // their work
+  __builtin_amdgcn_s_setprio(2);
 #pragma unroll
-    for (int r = 0; r < SROUNDS; r++) {
-      const int f = base + tid + WG * r;
-      // cell of entry f: the first staged cell whose inclusive prefix exceeds f
-      int m = 0;
-#pragma unroll
-      for (int step = 32; step >= 1; step >>= 1)
-        if (__shfl(incl, m + step - 1) <= f) m += step;
-      const int k = f - __shfl(pre, m & 63);
-      const int cm = __shfl(R.nc, m & 63);
-      mm[r] = m;
-      x[r] = y[r] = z[r] = 0.0;
-      if (f < stot) {
-        const gdouble* jb = cblk(cells, cm);
-        x[r] = jb[k];
-        y[r] = jb[CELL_CAP + k];
-        z[r] = jb[2 * CELL_CAP + k];
-      }
+  for (int i = 0; i < SROUNDS; i++) {
+    const int m = m0 + 16 * i;
+    // every lane takes part in the exchanges (a lane reading another lane's register
+    // needs that lane active)
+    const int cnt = __shfl(R.cnt, m);
+    const int cell = __shfl(R.nc, m);
+    const int first = __shfl(pre, m);
+    const bool have = m < nst && j < cnt;
+    pi[i] = have ? first + j : -1;
+    ex[i] = m < nst ? max(cnt - 16, 0) : 0;
+    x[i] = y[i] = z[i] = 0.0;
+    if (have) {
+      const gdouble* jb = cblk(cells, cell);
+      x[i] = jb[j];
+      y[i] = jb[CELL_CAP + j];
+      z[i] = jb[2 * CELL_CAP + j];
     }
-    __builtin_amdgcn_s_setprio(0);
-#pragma unroll
-    for (int r = 0; r < SROUNDS; r++) {
-      const int f = base + tid + WG * r;
-      if (f < stot) stage_put<PREC>(g, R, L, mm[r], f, x[r], y[r], z[r], wrap);
+  }
+  // the slots past the 16th of the quarter's cells, concatenated: 16 of them per pass, the
+  // first pass issued with the loads above
+  static_assert(SROUNDS == 4, "the extra-slot split below assumes four rounds");
+  const int e1 = ex[0], e2 = e1 + ex[1], e3 = e2 + ex[2], etot = e3 + ex[3];
+  auto extra = [&](int v, int& m, int& p, double& xv, double& yv, double& zv) {
+    const int i = (v >= e1 ? 1 : 0) + (v >= e2 ? 1 : 0) + (v >= e3 ? 1 : 0);
+    const int k = 16 + v - (i == 0 ? 0 : (i == 1 ? e1 : (i == 2 ? e2 : e3)));
+    m = m0 + 16 * i;
+    const int cell = __shfl(R.nc, m);
+    const int first = __shfl(pre, m);
+    p = v < etot ? first + k : -1;
+    xv = yv = zv = 0.0;
+    if (v < etot) {
+      const gdouble* jb = cblk(cells, cell);
+      xv = jb[k];
+      yv = jb[CELL_CAP + k];
+      zv = jb[2 * CELL_CAP + k];
     }
-    // every round's registers are read on every path: otherwise a load whose value is
-    // (in the compiler's view) left unread looks outstanding at the next pass, and each
-    // round then waits for the loads of the round before it
+  };
+  int me, pe;
+  double xe, ye, ze;
+  extra(j, me, pe, xe, ye, ze);
+  __builtin_amdgcn_s_setprio(0);
+  double o[3];
+  block_origin(g, R.gx, R.gy, R.z0, o);
 #pragma unroll
-    for (int r = 0; r < SROUNDS; r++) asm volatile("" ::"v"(x[r]), "v"(y[r]), "v"(z[r]));
+  for (int i = 0; i < SROUNDS; i++)
+    if (pi[i] >= 0) stage_put<PREC>(g, R, L, o, m0 + 16 * i, pi[i], x[i], y[i], z[i], wrap);
+  if (pe >= 0) stage_put<PREC>(g, R, L, o, me, pe, xe, ye, ze, wrap);
+  // every round's registers are read on every path: otherwise a load whose value is (in
+  // the compiler's view) left unread looks outstanding later, and a later wait for other
+  // loads also waits for it
+#pragma unroll
+  for (int i = 0; i < SROUNDS; i++) asm volatile("" ::"v"(x[i]), "v"(y[i]), "v"(z[i]));
+  asm volatile("" ::"v"(xe), "v"(ye), "v"(ze));
+  // more than 16 extra slots in some quarter (dense cells): the rest, a pass at a time
+  for (int v0 = 16; __ballot(v0 < etot); v0 += 16) {
+    extra(v0 + j, me, pe, xe, ye, ze);
+    if (pe >= 0) stage_put<PREC>(g, R, L, o, me, pe, xe, ye, ze, wrap);
   }
   __syncthreads();
   return nb;
