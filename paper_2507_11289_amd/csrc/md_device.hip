@@ -796,43 +796,74 @@ __device__ void block_force64(const DGeom& g, const BlockLDS<0>& L, int w, Force
       m = __builtin_amdgcn_alignbit(m, __float_as_uint(d[2]), 31);
       return __builtin_amdgcn_alignbit(m, __float_as_uint(d[3]), 31);
     };
-    for (int tb = 0; tb < ntile; tb += 8) {
-      const int cn = min(8, ntile - tb);
-      unsigned m = 0u;
-      if (cn == 8) {
-        float av[8];
+    for (int tg = 0; tg < ntile; tg += 8 * GMASKS) {
+      // groups of up to GMASKS batches of 8 tiles, one mask word per batch (in registers)
+      const int nw = min(GMASKS, (ntile - tg + 7) >> 3);
+      unsigned wd[GMASKS];
 #pragma unroll
-        for (int t = 0; t < 8; t++) av[t] = comp32(r0 + 16 * (tb + t));
+      for (int bi = 0; bi < GMASKS; bi++) {
+        wd[bi] = 0u;
+        if (bi < nw) {
+          const int tb = tg + 8 * bi;
+          const int cn = min(8, ntile - tb);
+          unsigned m = 0u;
+          if (cn == 8) {
+            float av[8];
 #pragma unroll
-        for (int t = 0; t < 8; t++) m = mark(m, av[t]);
-      } else {
-        for (int t = 0; t < cn; t++) m = mark(m, comp32(r0 + 16 * (tb + t)));
-        m <<= 32 - 4 * cn;
+            for (int t = 0; t < 8; t++) av[t] = comp32(r0 + 16 * (tb + t));
+#pragma unroll
+            for (int t = 0; t < 8; t++) m = mark(m, av[t]);
+          } else {
+            for (int t = 0; t < cn; t++) m = mark(m, comp32(r0 + 16 * (tb + t)));
+            m <<= 32 - 4 * cn;
+          }
+          // bit b marks candidate 4 b + quarter of the batch; candidates at or past the
+          // end of the window are dropped (with raw positions a periodic copy of a window
+          // cell there could otherwise be counted twice)
+          m = __builtin_bitreverse32(m);
+          const int fb = beg + 16 * tb + quarter;
+          const int nvalid = (fe - fb + 3) >> 2;
+          if (nvalid < 32) m &= nvalid > 0 ? (1u << nvalid) - 1u : 0u;
+          wd[bi] = m;
+        }
       }
-      // bit b marks candidate 4 b + quarter of the batch; candidates at or past the end
-      // of the window are dropped (with raw positions a periodic copy of a window cell
-      // there could otherwise be counted twice)
-      m = __builtin_bitreverse32(m);
-      const int fb = beg + 16 * tb + quarter;
-      const int nvalid = (fe - fb + 3) >> 2;
-      if (nvalid < 32) m &= nvalid > 0 ? (1u << nvalid) - 1u : 0u;
-      auto pairs = [&](auto wrap_c) {
+      // Pass 2: each lane walks its own words in order, the marked pairs two at a time and
+      // lowest bit first, moving to its next word as soon as one is used up (lanes do not
+      // wait for each other at word ends).  A missing pair is the lane's own atom (r2 = 0:
+      // not in range, adds exactly nothing), so every lane makes the calls of a word-by-word
+      // walk in the same order.
+      const int fb0 = beg + 16 * tg + quarter;
+      const int last = nw - 1;
+      auto walk = [&](auto wrap_c) {
         constexpr bool WRAP = decltype(wrap_c)::value;
-        while (m) {
+        // the words not yet reached move down one place at every word end (registers
+        // only: an indexed choice would put them in scratch memory)
+        unsigned m = wd[0], w1 = wd[1], w2 = wd[2], w3 = wd[3];
+        int k = 0;
+        while (m != 0u || k < last) {
+          if (m == 0u) {
+            k++;
+            m = w1;
+            w1 = w2;
+            w2 = w3;
+          }
+          const int fbb = fb0 + 128 * k;
+          const bool one = m != 0u;
           const int b1 = __ffs(m) - 1;
           m &= m - 1u;
           const bool two = m != 0u;
           const int b2 = __ffs(m) - 1;
           m &= m - 1u;
-          const int f1 = fb + 4 * b1, f2 = two ? fb + 4 * b2 : ia;
+          const int f1 = one ? fbb + 4 * b1 : ia, f2 = two ? fbb + 4 * b2 : ia;
           pair64<ENERGY, COUNT, WRAP>(g, xi, yi, zi, L.x[f1], L.y[f1], L.z[f1], A);
           pair64<ENERGY, COUNT, WRAP>(g, xi, yi, zi, L.x[f2], L.y[f2], L.z[f2], A);
         }
       };
+      static_assert(GMASKS == 4, "the word selection of the walk assumes four words");
       if (wrap)
-        pairs(std::true_type());
+        walk(std::true_type());
       else
-        pairs(std::false_type());
+        walk(std::false_type());
     }
     // quarter partials of column col, added in quarter order; lane 16 u + col keeps them
     const double sx = ((__shfl(A.fx, col) + __shfl(A.fx, col + 16)) + __shfl(A.fx, col + 32)) + __shfl(A.fx, col + 48);
