@@ -180,7 +180,10 @@ struct BlockHdr {
   int cnt[BCELLS];         // atoms of staged cell m
   int pre[BCELLS + 1];     // first staged entry of cell m
   double org[3];           // origin of the block's FP32 coordinates
+  int gx, gy, z0;          // the block: cells z0 .. z0 + nb - 1 of column (gx, gy)
   int nb;                  // cells of this block (after the capacity check)
+  int nst;                 // staged cells, 9 (nb + 2)
+  int wrap;                // some staged cell is a periodic image
   int wrap_col;            // the column touches a periodic boundary in x or y
   int wrap_layer[BLAYERS]; // z layer is a periodic image
 };
@@ -189,13 +192,14 @@ template <int PREC> struct BlockLDS;
 constexpr int GMASKS = 4;  // pre-filter mask words kept per lane: one group of the pair walk and the
                            // guard-band pass (32 tiles)
 template <> struct BlockLDS<1> {  // FP32: positions relative to the block origin, |q|^2
-  BlockHdr h;
+  BlockHdr hb[2];                 // headers of the current and the next block
   float4 q[CAPB + QPAD];
   unsigned gmask[WAVES][GMASKS + 1][64];  // each wave's pass-1 marks of its current atom batch
                                          // (and a padding word read ahead, never used)
 };
 template <> struct BlockLDS<0> {  // FP64: raw positions, plus per entry the periodic image
-  BlockHdr h;                     // and the FP32 |q|^2 of the matrix-core pre-filter
+  BlockHdr hb[2];                 // and the FP32 |q|^2 of the matrix-core pre-filter; headers
+                                  // of the current and the next block
   double x[CAPB + QPAD], y[CAPB + QPAD], z[CAPB + QPAD];
   float qn[CAPB + QPAD];
   uint8_t img[CAPB + QPAD];       // (sx + 1) | (sy + 1) << 2 | (sz + 1) << 4: image shift s L
@@ -304,16 +308,16 @@ __device__ __forceinline__ void pair64(const DGeom& g, double xi, double yi, dou
 }
 
 // Staging of the block of the column (gx, gy) whose cells start at z0 (at most nb_max
-// of them, all in the column), in two halves:
-//   stage_issue: every wave loads the atom counts of the block's cells (lane m: staged
-//     cell m) -- issued one block ahead, so they arrive while the previous block is
-//     integrated;
-//   stage_commit: prefix of the counts, capacity check, header; then each quarter wave
-//     (16 lanes) takes whole staged cells, one atom slot per lane: cell
-//     16 i + 4 w + quarter of wave w for i < SROUNDS, all of them loaded at once (one
-//     memory round trip for the whole block), then written into LDS at the cell's
-//     place in the compact staged list.  Atoms past the 16th of a cell follow in a
-//     second, rarely needed pass.
+// of them, all in the column).  One wave prepares each block's header:
+//   hdr_issue: lane m loads the atom count of staged cell m -- one block ahead, so the
+//     counts arrive while the previous block is integrated;
+//   hdr_commit: prefix of the counts, capacity check, header (double-buffered, so the
+//     next block's header is written while the current one is in use).
+// Then the whole workgroup stages the block (stage_fill): each quarter wave (16 lanes)
+// takes whole staged cells, one atom slot per lane: cell 16 i + 4 w + quarter of wave w
+// for i < SROUNDS, all of them loaded at once (one memory round trip for the whole
+// block), then written into LDS at the cell's place in the compact staged list.  The
+// slots past the 16th of a quarter's cells follow, concatenated, in one more batch.
 // ---------------------------------------------------------------------------
 constexpr int SROUNDS = (BCELLS + 15) / 16;  // staged cells per quarter wave
 static_assert(16 * SROUNDS <= 64, "a staged cell index must name a lane of the wave");
@@ -339,8 +343,8 @@ __device__ __forceinline__ void staged_cell_xyz(int gx, int gy, int z0, int m, i
   nz = z0 - 1 + lay;
 }
 
-__device__ __forceinline__ void stage_issue(const DGeom& g, const uint32_t* ncnt, int gx, int gy, int z0,
-                                            int nb_max, StageRegs& R) {
+__device__ __forceinline__ void hdr_issue(const DGeom& g, const uint32_t* ncnt, int gx, int gy, int z0,
+                                          int nb_max, StageRegs& R) {
   const int lane = __lane_id();
   R.gx = gx;
   R.gy = gy;
@@ -379,7 +383,7 @@ __device__ __forceinline__ float rel32(double x, int s, double L, double o) {
 // wrap: some staged cell of the block is a periodic image (its coordinates are shifted
 // by a box length); without it every shift is 0.
 template <int PREC>
-__device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, BlockLDS<PREC>& L, const double o[3],
+__device__ __forceinline__ void stage_put(const DGeom& g, const BlockHdr& H, BlockLDS<PREC>& L, const double o[3],
                                           int m, int p, double x, double y, double z, bool wrap) {
   if constexpr (PREC == 1) {
     float qx, qy, qz;
@@ -389,7 +393,7 @@ __device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, Bl
       qz = (float)sub_rn(z, o[2]);
     } else {
       int nx, ny, nz;
-      staged_cell_xyz(R.gx, R.gy, R.z0, m, nx, ny, nz);
+      staged_cell_xyz(H.gx, H.gy, H.z0, m, nx, ny, nz);
       const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
       const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
       const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
@@ -406,7 +410,7 @@ __device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, Bl
     int sx = 0, sy = 0, sz = 0;
     if (wrap) {
       int nx, ny, nz;
-      staged_cell_xyz(R.gx, R.gy, R.z0, m, nx, ny, nz);
+      staged_cell_xyz(H.gx, H.gy, H.z0, m, nx, ny, nz);
       sx = nx < 0 ? -1 : (nx >= g.G[0] ? 1 : 0);
       sy = ny < 0 ? -1 : (ny >= g.G[1] ? 1 : 0);
       sz = nz < 0 ? -1 : (nz >= g.G[2] ? 1 : 0);
@@ -420,54 +424,64 @@ __device__ __forceinline__ void stage_put(const DGeom& g, const StageRegs& R, Bl
   }
 }
 
-// Returns the cells actually taken (capacity may shorten the block).  Whole
-// workgroup; the LDS must be free on entry; ends with a barrier.
+// Header of the block from the counts of hdr_issue: prefix, capacity check (the largest
+// nb whose 9 (nb + 2) cells fit; nb = 1 always fits).  One wave.
 template <int PREC>
-__device__ int stage_commit(const DGeom& g, const unsigned char* cells, const StageRegs& R, BlockLDS<PREC>& L) {
+__device__ void hdr_commit(const DGeom& g, const StageRegs& R, BlockHdr& H) {
   const int lane = __lane_id();
-  const int w = threadIdx.x >> 6;
   int incl = R.cnt;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
     const int v = __shfl_up(incl, off);
     if (lane >= off) incl += v;
   }
-  const int pre = incl - R.cnt;
-  // largest nb with its 9 (nb + 2) cells within capacity (nb = 1 always fits)
   int nb = R.nb_max;
   while (nb > 1 && __shfl(incl, 9 * (nb + 2) - 1) > CAPB) nb--;
-  const int nst = 9 * (nb + 2);
-  const int stot = __shfl(incl, nst - 1);
-  if (w == 0) {
-    if (lane < BCELLS) {
-      L.h.nb_cell[lane] = R.nc;
-      L.h.cnt[lane] = R.cnt;
-      L.h.pre[lane] = pre;
-    }
-    if (lane == BCELLS - 1) L.h.pre[BCELLS] = incl;
-    if (lane == 0) {
-      L.h.nb = nb;
-      L.h.wrap_col = R.gx == 0 || R.gx == g.G[0] - 1 || R.gy == 0 || R.gy == g.G[1] - 1;
-      if constexpr (PREC == 0) block_origin(g, R.gx, R.gy, R.z0, L.h.org);
-    }
-    if (lane < BLAYERS) {
-      const int nz = R.z0 - 1 + lane;
-      L.h.wrap_layer[lane] = nz < 0 || nz >= g.G[2];
-    }
+  if (lane < BCELLS) {
+    H.nb_cell[lane] = R.nc;
+    H.cnt[lane] = R.cnt;
+    H.pre[lane] = incl - R.cnt;
+  }
+  if (lane == BCELLS - 1) H.pre[BCELLS] = incl;
+  if (lane == 0) {
+    H.gx = R.gx;
+    H.gy = R.gy;
+    H.z0 = R.z0;
+    H.nb = nb;
+    H.nst = 9 * (nb + 2);
+    H.wrap_col = R.gx == 0 || R.gx == g.G[0] - 1 || R.gy == 0 || R.gy == g.G[1] - 1;
+    H.wrap = H.wrap_col || R.z0 == 0 || R.z0 + nb >= g.G[2];
+    if constexpr (PREC == 0) block_origin(g, R.gx, R.gy, R.z0, H.org);
+  }
+  if (lane < BLAYERS) {
+    const int nz = R.z0 - 1 + lane;
+    H.wrap_layer[lane] = nz < 0 || nz >= g.G[2];
+  }
+}
+
+// Stage the block of header H into LDS.  With OWN, every wave also loads the position,
+// velocity and id of its own cell's atoms into o (issued after the staging loads, so the
+// staging waits leave them in flight).  Whole workgroup; the LDS entries must be free and
+// H complete on entry; ends with a barrier.
+template <int PREC, bool OWN>
+__device__ void stage_fill(const DGeom& g, const unsigned char* cells, const BlockHdr& H, BlockLDS<PREC>& L,
+                           ForceOut& own) {
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  const int nst = H.nst;
+  const bool wrap = H.wrap;
+  if (w == 0 && lane < QPAD) {
     // far sentinels after the last staged atom: a pair-loop read past the end of the
     // list finds no partner in range
-    if (lane < QPAD) {
-      if constexpr (PREC == 1) {
-        L.q[stot + lane] = far_entry();
-      } else {
-        L.x[stot + lane] = L.y[stot + lane] = L.z[stot + lane] = (double)FAR_Q;
-        L.qn[stot + lane] = 3.0f * FAR_Q * FAR_Q;
-        L.img[stot + lane] = IMG_NONE;
-      }
+    const int stot = H.pre[nst];
+    if constexpr (PREC == 1) {
+      L.q[stot + lane] = far_entry();
+    } else {
+      L.x[stot + lane] = L.y[stot + lane] = L.z[stot + lane] = (double)FAR_Q;
+      L.qn[stot + lane] = 3.0f * FAR_Q * FAR_Q;
+      L.img[stot + lane] = IMG_NONE;
     }
   }
-  const bool wrap = R.gx == 0 || R.gx == g.G[0] - 1 || R.gy == 0 || R.gy == g.G[1] - 1 || R.z0 == 0 ||
-                    R.z0 + nb >= g.G[2];
   // staged cell of round 0 (round i: m0 + 16 i), i.e. 4 w + quarter; recomputed here so
   // that the per-round indices are not hoisted out of the block loop and held in registers
   const int tid = opaque_tid();
@@ -482,14 +496,12 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
 #pragma unroll
   for (int i = 0; i < SROUNDS; i++) {
     const int m = m0 + 16 * i;
-    // every lane takes part in the exchanges (a lane reading another lane's register
-    // needs that lane active)
-    const int cnt = __shfl(R.cnt, m);
-    const int cell = __shfl(R.nc, m);
-    const int first = __shfl(pre, m);
-    const bool have = m < nst && j < cnt;
-    pi[i] = have ? first + j : -1;
-    ex[i] = m < nst ? max(cnt - 16, 0) : 0;
+    const int ms = m < BCELLS ? m : 0;
+    const int cnt = m < nst ? H.cnt[ms] : 0;
+    const int cell = H.nb_cell[ms];
+    const bool have = j < cnt;
+    pi[i] = have ? H.pre[ms] + j : -1;
+    ex[i] = max(cnt - 16, 0);
     x[i] = y[i] = z[i] = 0.0;
     if (have) {
       const gdouble* jb = cblk(cells, cell);
@@ -506,12 +518,11 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
     const int i = (v >= e1 ? 1 : 0) + (v >= e2 ? 1 : 0) + (v >= e3 ? 1 : 0);
     const int k = 16 + v - (i == 0 ? 0 : (i == 1 ? e1 : (i == 2 ? e2 : e3)));
     m = m0 + 16 * i;
-    const int cell = __shfl(R.nc, m);
-    const int first = __shfl(pre, m);
-    p = v < etot ? first + k : -1;
+    p = -1;
     xv = yv = zv = 0.0;
     if (v < etot) {
-      const gdouble* jb = cblk(cells, cell);
+      const gdouble* jb = cblk(cells, H.nb_cell[m]);
+      p = H.pre[m] + k;
       xv = jb[k];
       yv = jb[CELL_CAP + k];
       zv = jb[2 * CELL_CAP + k];
@@ -520,13 +531,27 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
   int me, pe;
   double xe, ye, ze;
   extra(j, me, pe, xe, ye, ze);
+  if (OWN) {
+    // the wave's own cell (none if the capacity check dropped it)
+    const int ci = 9 * (w + 1) + 4;
+    const int n_own = w < H.nb ? H.cnt[ci] : 0;
+    if (lane < n_own) {
+      const gdouble* ib = cblk(cells, H.nb_cell[ci]);
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        own.x[d] = ib[d * CELL_CAP + lane];
+        own.v[d] = ib[(3 + d) * CELL_CAP + lane];
+      }
+      own.id = cids(ib)[lane];
+    }
+  }
   __builtin_amdgcn_s_setprio(0);
   double o[3];
-  block_origin(g, R.gx, R.gy, R.z0, o);
+  block_origin(g, H.gx, H.gy, H.z0, o);
 #pragma unroll
   for (int i = 0; i < SROUNDS; i++)
-    if (pi[i] >= 0) stage_put<PREC>(g, R, L, o, m0 + 16 * i, pi[i], x[i], y[i], z[i], wrap);
-  if (pe >= 0) stage_put<PREC>(g, R, L, o, me, pe, xe, ye, ze, wrap);
+    if (pi[i] >= 0) stage_put<PREC>(g, H, L, o, m0 + 16 * i, pi[i], x[i], y[i], z[i], wrap);
+  if (pe >= 0) stage_put<PREC>(g, H, L, o, me, pe, xe, ye, ze, wrap);
   // every round's registers are read on every path: otherwise a load whose value is (in
   // the compiler's view) left unread looks outstanding later, and a later wait for other
   // loads also waits for it
@@ -536,20 +561,9 @@ __device__ int stage_commit(const DGeom& g, const unsigned char* cells, const St
   // more than 16 extra slots in some quarter (dense cells): the rest, a pass at a time
   for (int v0 = 16; __ballot(v0 < etot); v0 += 16) {
     extra(v0 + j, me, pe, xe, ye, ze);
-    if (pe >= 0) stage_put<PREC>(g, R, L, o, me, pe, xe, ye, ze, wrap);
+    if (pe >= 0) stage_put<PREC>(g, H, L, o, me, pe, xe, ye, ze, wrap);
   }
   __syncthreads();
-  return nb;
-}
-
-// Both halves at once (the synchronous read-back path).  Whole workgroup.
-template <int PREC>
-__device__ int stage_block(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int gx, int gy,
-                           int z0, int nb_max, BlockLDS<PREC>& L) {
-  StageRegs R;
-  stage_issue(g, ncnt, gx, gy, z0, nb_max, R);
-  __syncthreads();
-  return stage_commit<PREC>(g, cells, R, L);
 }
 
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
@@ -570,15 +584,15 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 // An atom's four quarter partials are added as (q0 + q1) + (q2 + q3), so every sum has a
 // fixed order.  Wave-level (no barrier).
 template <bool ENERGY, bool COUNT>
-__device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockLDS<1>& L, int w,
-                              ForceOut& o) {
+__device__ void block_force32(const DGeom& g, const unsigned char* cells, const BlockHdr& H, BlockLDS<1>& L,
+                              int w, ForceOut& o) {
   const int lane = __lane_id();
   const int col = lane & 15, quarter = lane >> 4;
   const int n_i = o.n;
   const int ci = 9 * (w + 1) + 4;
-  const int beg = L.h.pre[9 * w];
+  const int beg = H.pre[9 * w];
   const int fe = beg + o.total;
-  const int si = L.h.pre[ci];  // own atoms in the staged list
+  const int si = H.pre[ci];  // own atoms in the staged list
   // tiles of the window; the last one may reach up to 15 entries past its end, into the
   // next z layer (two cells above the own cell: out of range) or the far sentinels
   const int ntile = __builtin_amdgcn_readfirstlane((o.total + 15) >> 4);
@@ -688,9 +702,9 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
           int sm = 0;
 #pragma unroll
           for (int step = 32; step >= 1; step >>= 1)
-            if (sm + step < BCELLS && L.h.pre[sm + step] <= f) sm += step;
-          const gdouble* jb = cblk(cells, L.h.nb_cell[sm]);
-          const int k = f - L.h.pre[sm];
+            if (sm + step < BCELLS && H.pre[sm + step] <= f) sm += step;
+          const gdouble* jb = cblk(cells, H.nb_cell[sm]);
+          const int k = f - H.pre[sm];
           const double ex = min_img(sub_rn(xi, jb[k]), g.L[0], g.halfL[0]);
           const double ey = min_img(sub_rn(yi, jb[CELL_CAP + k]), g.L[1], g.halfL[1]);
           const double ez = min_img(sub_rn(zi, jb[2 * CELL_CAP + k]), g.L[2], g.halfL[2]);
@@ -757,20 +771,20 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, BlockL
 // pair-by-pair FP64 loop makes.  Quarter partials are added in quarter order.
 // Wave-level (no barrier).
 template <bool ENERGY, bool COUNT>
-__device__ void block_force64(const DGeom& g, const BlockLDS<0>& L, int w, ForceOut& o) {
+__device__ void block_force64(const DGeom& g, const BlockHdr& H, const BlockLDS<0>& L, int w, ForceOut& o) {
   const int lane = __lane_id();
   const int col = lane & 15, quarter = lane >> 4;
   const int n_i = o.n;
   const int ci = 9 * (w + 1) + 4;
-  const int beg = L.h.pre[9 * w];
+  const int beg = H.pre[9 * w];
   const int fe = beg + o.total;
-  const int si = L.h.pre[ci];  // own atoms in the staged list
+  const int si = H.pre[ci];  // own atoms in the staged list
   const int ntile = __builtin_amdgcn_readfirstlane((o.total + 15) >> 4);
-  const bool wrap = L.h.wrap_col || L.h.wrap_layer[w] || L.h.wrap_layer[w + 2];
+  const bool wrap = H.wrap_col || H.wrap_layer[w] || H.wrap_layer[w + 2];
   // the component this lane supplies to the matrix ops (3: |q|^2)
   const int kc = quarter < 3 ? quarter : 2;
   const double* X = kc == 0 ? L.x : (kc == 1 ? L.y : L.z);
-  const double Lk = g.L[kc], ok = L.h.org[kc];
+  const double Lk = g.L[kc], ok = H.org[kc];
   auto comp32 = [&](int f) {
     if (quarter == 3) return L.qn[f];
     const int s = (((int)L.img[f] >> (2 * kc)) & 3) - 1;
@@ -891,31 +905,33 @@ __device__ void block_force64(const DGeom& g, const BlockLDS<0>& L, int w, Force
 // Pair forces of every atom of the cell of this wave in the staged block: header of
 // the wave's cell, then the FP32 or FP64 pair loop.  Whole workgroup.
 template <int PREC, bool ENERGY, bool COUNT>
-__device__ void block_force(const DGeom& g, const unsigned char* cells, BlockLDS<PREC>& L, ForceOut& o) {
+__device__ void block_force(const DGeom& g, const unsigned char* cells, const BlockHdr& H, BlockLDS<PREC>& L,
+                            ForceOut& o) {
   const int w = threadIdx.x >> 6;
-  const bool mine = w < L.h.nb;
+  const bool mine = w < H.nb;
   const int ci = 9 * (w + 1) + 4;  // staged index of the wave's own cell
-  o.n = mine ? L.h.cnt[ci] : 0;
-  o.total = mine ? L.h.pre[9 * (w + 3)] - L.h.pre[9 * w] : 0;
-  o.c = mine ? L.h.nb_cell[ci] : -1;
+  o.n = mine ? H.cnt[ci] : 0;
+  o.total = mine ? H.pre[9 * (w + 3)] - H.pre[9 * w] : 0;
+  o.c = mine ? H.nb_cell[ci] : -1;
   o.fx = o.fy = o.fz = 0.0;
   o.uh = o.wh = 0.0;
   o.pc = 0;
   if constexpr (PREC == 1)
-    block_force32<ENERGY, COUNT>(g, cells, L, w, o);
+    block_force32<ENERGY, COUNT>(g, cells, H, L, w, o);
   else
-    block_force64<ENERGY, COUNT>(g, L, w, o);
+    block_force64<ENERGY, COUNT>(g, H, L, w, o);
 }
 
 // Walk the cells [b, e) of one slice (local indices, z fastest) block by block; fn(o)
-// runs on every wave after each block's forces, while the counts of the next block are
-// in flight.  With OWN, the position, velocity and id of the wave's own atoms are loaded
-// right after staging and arrive during the pair loop.  Whole workgroup.
+// runs on every wave after each block's forces.  Wave 0 prepares the headers: the next
+// block's counts are loaded before fn and its header is written after it, while the
+// other waves wait for the next block.  With OWN, the position, velocity and id of the
+// wave's own atoms are loaded with the staging and arrive during the pair loop.  Whole
+// workgroup.
 template <int PREC, bool ENERGY, bool COUNT, bool OWN, class Fn>
 __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int slice, int b,
                            int e, BlockLDS<PREC>& L, Fn&& fn) {
   if (b >= e) return;
-  const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   // blocks stay within the column and within one aligned group of BZ cells
   auto issue = [&](int xs, StageRegs& R) {
@@ -925,44 +941,36 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
     const int gy = t - u * g.G[1];
     const int gx = slice * g.ncx + u;
     const int nb_max = min(min(BZ - gz % BZ, e - xs), g.G[2] - gz);
-    stage_issue(g, ncnt, gx, gy, gz, nb_max, R);
+    hdr_issue(g, ncnt, gx, gy, gz, nb_max, R);
   };
   StageRegs R;
-  int x = b;
-  issue(x, R);
+  int x = b, hb = 0;
+  if (w == 0) {
+    issue(x, R);
+    hdr_commit<PREC>(g, R, L.hb[0]);
+  }
   while (true) {
+    __syncthreads();  // every wave is done with the previous block's LDS; header hb is complete
+    const BlockHdr& H = L.hb[hb];
     ForceOut o;
+    stage_fill<PREC, OWN>(g, cells, H, L, o);
+    block_force<PREC, ENERGY, COUNT>(g, cells, H, L, o);
     if (OWN) {
-      // issued before the block is staged (the capacity check may still drop this cell;
-      // the data is then unused), so it has arrived before the pair loop needs registers
-      const int ci = 9 * (w + 1) + 4;
-      const int n_own = w < R.nb_max ? __shfl(R.cnt, ci) : 0;
-      const int c_own = __shfl(R.nc, ci);
-      if (lane < n_own) {
-        const gdouble* ib = cblk(cells, c_own);
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-          o.x[d] = ib[d * CELL_CAP + lane];
-          o.v[d] = ib[(3 + d) * CELL_CAP + lane];
-        }
-        o.id = cids(ib)[lane];
-      }
-    }
-    __syncthreads();  // every wave is done with the previous block's LDS
-    const int nb = stage_commit<PREC>(g, cells, R, L);
-    if (OWN) {
-      // the barriers have waited for the own cell's loads; from here on its values count
+      // the pair loop has covered the own cell's loads; from here on their values count
       // as plain registers, so the tail does not wait for the next block's count loads
       // (issued just before it) on their account
       asm volatile("" : "+v"(o.id), "+v"(o.x[0]), "+v"(o.x[1]), "+v"(o.x[2]), "+v"(o.v[0]), "+v"(o.v[1]),
                    "+v"(o.v[2]));
     }
-    block_force<PREC, ENERGY, COUNT>(g, cells, L, o);
-    x += nb;
+    x += H.nb;
     const bool more = x < e;
-    if (more) issue(x, R);
+    if (more && w == 0) issue(x, R);
     fn(o);
     if (!more) break;
+    // the other header is free: every wave finished the block that used it before the
+    // barrier above
+    if (w == 0) hdr_commit<PREC>(g, R, L.hb[hb ^ 1]);
+    hb ^= 1;
   }
 }
 
