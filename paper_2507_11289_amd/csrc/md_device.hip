@@ -459,13 +459,22 @@ __device__ void hdr_commit(const DGeom& g, const StageRegs& R, BlockHdr& H) {
   }
 }
 
-// Stage the block of header H into LDS.  With OWN, every wave also loads the position,
-// velocity and id of its own cell's atoms into o (issued after the staging loads, so the
-// staging waits leave them in flight).  Whole workgroup; the LDS entries must be free and
-// H complete on entry; ends with a barrier.
-template <int PREC, bool OWN>
+// Atoms of the block's own cells, in cell order (at most BZ cells).
+__device__ __forceinline__ int block_atoms(const BlockHdr& H) {
+  int t = 0;
+#pragma unroll
+  for (int q = 0; q < BZ; q++) t += q < H.nb ? H.cnt[9 * (q + 1) + 4] : 0;
+  return t;
+}
+
+// Stage the block of header H into LDS.  own_mode 1: every wave also loads the position,
+// velocity and id of its own cell's atoms into own; 2: wave tw loads those of all the
+// block's cells, atom l of them (in cell order) on lane l (at most 64).  These loads are
+// issued after the staging loads, so the staging waits leave them in flight.  Whole
+// workgroup; the LDS entries must be free and H complete on entry; ends with a barrier.
+template <int PREC>
 __device__ void stage_fill(const DGeom& g, const unsigned char* cells, const BlockHdr& H, BlockLDS<PREC>& L,
-                           ForceOut& own) {
+                           ForceOut& own, int own_mode, int tw) {
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   const int nst = H.nst;
@@ -531,18 +540,30 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, const Blo
   int me, pe;
   double xe, ye, ze;
   extra(j, me, pe, xe, ye, ze);
-  if (OWN) {
-    // the wave's own cell (none if the capacity check dropped it)
-    const int ci = 9 * (w + 1) + 4;
-    const int n_own = w < H.nb ? H.cnt[ci] : 0;
-    if (lane < n_own) {
-      const gdouble* ib = cblk(cells, H.nb_cell[ci]);
+  if (own_mode == 1 || (own_mode == 2 && w == tw)) {
+    // own_mode 1: the wave's own cell (none if the capacity check dropped it); 2: cell q
+    // of the block holds atoms [P_q, P_q + n_q) of the lanes
+    int q = w, k = lane, nq = w < H.nb ? H.cnt[9 * (w + 1) + 4] : 0;
+    if (own_mode == 2) {
+      int nr[BZ], P[BZ + 1];
+      P[0] = 0;
+#pragma unroll
+      for (int r = 0; r < BZ; r++) {
+        nr[r] = r < H.nb ? H.cnt[9 * (r + 1) + 4] : 0;
+        P[r + 1] = P[r] + nr[r];
+      }
+      q = (lane >= P[1] ? 1 : 0) + (lane >= P[2] ? 1 : 0) + (lane >= P[3] ? 1 : 0);
+      k = lane - (q == 0 ? 0 : (q == 1 ? P[1] : (q == 2 ? P[2] : P[3])));
+      nq = q == 0 ? nr[0] : (q == 1 ? nr[1] : (q == 2 ? nr[2] : nr[3]));
+    }
+    if (k < nq) {
+      const gdouble* ib = cblk(cells, H.nb_cell[9 * (q + 1) + 4]);
 #pragma unroll
       for (int d = 0; d < 3; d++) {
-        own.x[d] = ib[d * CELL_CAP + lane];
-        own.v[d] = ib[(3 + d) * CELL_CAP + lane];
+        own.x[d] = ib[d * CELL_CAP + k];
+        own.v[d] = ib[(3 + d) * CELL_CAP + k];
       }
-      own.id = cids(ib)[lane];
+      own.id = cids(ib)[k];
     }
   }
   __builtin_amdgcn_s_setprio(0);
@@ -922,15 +943,37 @@ __device__ void block_force(const DGeom& g, const unsigned char* cells, const Bl
     block_force64<ENERGY, COUNT>(g, H, L, w, o);
 }
 
+// Where the waves leave their forces for the wave that finishes the block: FP32 (the
+// sums are FP32 values), in each wave's own mask words, free once its pair loop is done;
+// FP64, in the staged-entry area, free once every wave's pair loop is done.  Force d of
+// atom k of wave q's cell at [q * FSTRIDE + 64 d + k].
+template <int PREC> struct BlockForces;
+template <> struct BlockForces<1> {
+  typedef float T;
+  static constexpr int FSTRIDE = (GMASKS + 1) * 64;
+  static constexpr bool AFTER_ALL = false;  // a wave may write as soon as its own pair loop is done
+  static __device__ __forceinline__ float* at(BlockLDS<1>& L) { return reinterpret_cast<float*>(&L.gmask[0][0][0]); }
+};
+template <> struct BlockForces<0> {
+  typedef double T;
+  static constexpr int FSTRIDE = 3 * 64;
+  static constexpr bool AFTER_ALL = true;   // every wave's pair loop must be done first
+  static __device__ __forceinline__ double* at(BlockLDS<0>& L) { return L.x; }
+};
+static_assert(sizeof(unsigned) * (GMASKS + 1) * 64 >= sizeof(float) * 3 * 64, "force scratch");
+static_assert(sizeof(double) * (CAPB + QPAD) >= sizeof(double) * WAVES * 3 * 64, "force scratch");
+
 // Walk the cells [b, e) of one slice (local indices, z fastest) block by block; fn(o)
 // runs on every wave after each block's forces.  Wave 0 prepares the headers: the next
 // block's counts are loaded before fn and its header is written after it, while the
 // other waves wait for the next block.  With OWN, the position, velocity and id of the
-// wave's own atoms are loaded with the staging and arrive during the pair loop.  Whole
-// workgroup.
-template <int PREC, bool ENERGY, bool COUNT, bool OWN, class Fn>
+// wave's own atoms are loaded with the staging and arrive during the pair loop.  With
+// BTAIL, a block whose cells hold at most 64 atoms is finished by one wave (taking turns
+// block by block): the waves leave their forces in LDS and fnb(H, o, forces, stride)
+// runs on that wave, whose lanes hold the block's atoms in cell order.  Whole workgroup.
+template <int PREC, bool ENERGY, bool COUNT, bool OWN, bool BTAIL, class Fn, class FnB>
 __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int slice, int b,
-                           int e, BlockLDS<PREC>& L, Fn&& fn) {
+                           int e, BlockLDS<PREC>& L, Fn&& fn, FnB&& fnb) {
   if (b >= e) return;
   const int w = threadIdx.x >> 6;
   // blocks stay within the column and within one aligned group of BZ cells
@@ -944,7 +987,7 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
     hdr_issue(g, ncnt, gx, gy, gz, nb_max, R);
   };
   StageRegs R;
-  int x = b, hb = 0;
+  int x = b, hb = 0, nblk = 0;
   if (w == 0) {
     issue(x, R);
     hdr_commit<PREC>(g, R, L.hb[0]);
@@ -952,8 +995,10 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
   while (true) {
     __syncthreads();  // every wave is done with the previous block's LDS; header hb is complete
     const BlockHdr& H = L.hb[hb];
+    const int tw = nblk & (WAVES - 1);
+    const bool one = BTAIL && block_atoms(H) <= 64;
     ForceOut o;
-    stage_fill<PREC, OWN>(g, cells, H, L, o);
+    stage_fill<PREC>(g, cells, H, L, o, OWN ? (one ? 2 : 1) : 0, tw);
     block_force<PREC, ENERGY, COUNT>(g, cells, H, L, o);
     if (OWN) {
       // the pair loop has covered the own cell's loads; from here on their values count
@@ -965,12 +1010,27 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
     x += H.nb;
     const bool more = x < e;
     if (more && w == 0) issue(x, R);
-    fn(o);
+    if (one) {
+      typedef BlockForces<PREC> BF;
+      typename BF::T* Fl = BF::at(L);
+      const int lane = __lane_id();
+      if (BF::AFTER_ALL) __syncthreads();  // every pair loop is done with the staged entries
+      if (lane < o.n) {
+        Fl[w * BF::FSTRIDE + lane] = (typename BF::T)o.fx;
+        Fl[w * BF::FSTRIDE + 64 + lane] = (typename BF::T)o.fy;
+        Fl[w * BF::FSTRIDE + 128 + lane] = (typename BF::T)o.fz;
+      }
+      __syncthreads();
+      if (w == tw) fnb(H, o, (const typename BF::T*)Fl, BF::FSTRIDE);
+    } else {
+      fn(o);
+    }
     if (!more) break;
     // the other header is free: every wave finished the block that used it before the
     // barrier above
     if (w == 0) hdr_commit<PREC>(g, R, L.hb[hb ^ 1]);
     hb ^= 1;
+    nblk++;
   }
 }
 
@@ -999,73 +1059,46 @@ __device__ __forceinline__ void acc_zero(ItemAcc& a) {
 // stored: the same cell (kept in order), or appended to another cell -- possibly in
 // the left or right neighbour slice.
 // ---------------------------------------------------------------------------
-// SCALE: the thermostat factor lam multiplies v(t) first (the forces come from the
-// thermostat's force pass; energies were sampled there).
-template <bool ENERGY, bool COUNT, bool SCALE>
-__device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old, int first, ItemAcc& acc,
-                        uint32_t* abort_flag, double lam) {
-  const DGeom& g = ra.g;
-  const int lane = __lane_id();
-  const int dst = src ^ 1;
-  const int c = o.c;
-  if (c < 0) return;
-  if (o.n == 0) {
-    if (lane == 0) gptr(ra.ncnt[dst])[c] = 0u;
-    return;
-  }
-  const bool own = lane < o.n;
-  double xn[3] = {0, 0, 0}, vh[3] = {0, 0, 0};
-  uint32_t id = 0;
-  int dest = c;
-  uint32_t bad = 0;
-  int dir = 0;  // 0 stay in slice, 1 left, 2 right
-  if (own) {
-    const double F[3] = {o.fx, o.fy, o.fz};
-    double vf[3];
+// The update of one atom: v(t) (vf), v(t + dt/2) (vh), the wrapped r(t + dt) (xn), its
+// cell (dest) and slice move (dir: 0 none, 1 left, 2 right); error bits in bad.
+// SCALE: the thermostat factor lam multiplies v(t) first.
+template <bool SCALE>
+__device__ __forceinline__ void advance(const DGeom& g, const double F[3], const double x[3], const double v[3],
+                                        int first, double lam, int s_old, double vf[3], double vh[3],
+                                        double xn[3], int& dest, int& dir, uint32_t& bad) {
 #pragma unroll
-    for (int d = 0; d < 3; d++) {
-      const double v = o.v[d];
-      vf[d] = first ? v : add_rn(v, mul_rn(g.hdt, F[d]));
-      if (SCALE) vf[d] = mul_rn(lam, vf[d]);
-    }
-    if (ENERGY) {
-      acc.k += 0.5 * add_rn(add_rn(mul_rn(vf[0], vf[0]), mul_rn(vf[1], vf[1])),
-                               mul_rn(vf[2], vf[2]));
-      acc.u += o.uh;
-      acc.w += o.wh;
-    }
-    if (COUNT) {
-      acc.cand += (unsigned long long)(o.total - 1);
-      acc.inr += o.pc;
-    }
-    int gc[3];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-      vh[d] = add_rn(vf[d], mul_rn(g.hdt, F[d]));
-      const double x = add_rn(o.x[d], mul_rn(g.dt, vh[d]));
-      xn[d] = wrap1(x, g.L[d]);
-      // NaN and infinite positions fail one of the two tests, and a non-finite velocity
-      // always gives a non-finite position (dt is finite and positive)
-      if (!(xn[d] >= 0.0) || xn[d] > g.L[d]) bad |= ERR_NONFINITE;
-      gc[d] = coord_cell(xn[d], g.inv_l[d], g.G[d]);
-    }
-    id = o.id;
-    const int s_new = qdiv(gc[0], g.inv_ncx);
-    dest = s_new * g.cps + ((gc[0] - s_new * g.ncx) * g.G[1] + gc[1]) * g.G[2] + gc[2];
-    int delta = s_new - s_old;  // both in [0, S): (s_new - s_old) mod S
-    if (delta < 0) delta += g.S;
-    if (delta == 1) dir = 2;
-    else if (delta == g.S - 1) dir = 1;
-    else if (delta != 0) bad |= ERR_DISPLACEMENT;
+  for (int d = 0; d < 3; d++) {
+    vf[d] = first ? v[d] : add_rn(v[d], mul_rn(g.hdt, F[d]));
+    if (SCALE) vf[d] = mul_rn(lam, vf[d]);
   }
-  if (bad) raise_error(ra.err, abort_flag, bad);
-  const bool ok = own && !bad;
-  const bool stay = ok && dest == c;
-  const unsigned long long sm = __ballot(stay);
+  int gc[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    vh[d] = add_rn(vf[d], mul_rn(g.hdt, F[d]));
+    const double xs = add_rn(x[d], mul_rn(g.dt, vh[d]));
+    xn[d] = wrap1(xs, g.L[d]);
+    // NaN and infinite positions fail one of the two tests, and a non-finite velocity
+    // always gives a non-finite position (dt is finite and positive)
+    if (!(xn[d] >= 0.0) || xn[d] > g.L[d]) bad |= ERR_NONFINITE;
+    gc[d] = coord_cell(xn[d], g.inv_l[d], g.G[d]);
+  }
+  const int s_new = qdiv(gc[0], g.inv_ncx);
+  dest = s_new * g.cps + ((gc[0] - s_new * g.ncx) * g.G[1] + gc[1]) * g.G[2] + gc[2];
+  int delta = s_new - s_old;  // both in [0, S): (s_new - s_old) mod S
+  if (delta < 0) delta += g.S;
+  if (delta == 1) dir = 2;
+  else if (delta == g.S - 1) dir = 1;
+  else if (delta != 0) bad |= ERR_DISPLACEMENT;
+}
+
+// Store of one updated atom: a stayer at its rank among the cell's stayers (id order
+// kept), a mover appended from the top slot of its new cell.
+__device__ __forceinline__ void store_atom(const RunArgs& ra, int dst, uint32_t* abort_flag, bool stay, bool ok,
+                                           int rank, int dest, const double xn[3], const double vh[3],
+                                           uint32_t id) {
   int slot = -1;
   if (stay) {
-    slot = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(sm >> 32),
-                                          __builtin_amdgcn_mbcnt_lo((unsigned)sm, 0u));
+    slot = rank;
   } else if (ok) {
     const unsigned old =
         __hip_atomic_fetch_add(gptr(ra.nin[dst]) + dest, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1081,7 +1114,103 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old
     }
     cids(ob)[slot] = id;
   }
+}
+
+// One cell per wave (lanes < o.n).  SCALE: the thermostat factor lam multiplies v(t)
+// first (the forces come from the thermostat's force pass; energies were sampled there).
+template <bool ENERGY, bool COUNT, bool SCALE>
+__device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old, int first, ItemAcc& acc,
+                        uint32_t* abort_flag, double lam) {
+  const DGeom& g = ra.g;
+  const int lane = __lane_id();
+  const int dst = src ^ 1;
+  const int c = o.c;
+  if (c < 0) return;
+  if (o.n == 0) {
+    if (lane == 0) gptr(ra.ncnt[dst])[c] = 0u;
+    return;
+  }
+  const bool own = lane < o.n;
+  double xn[3] = {0, 0, 0}, vh[3] = {0, 0, 0};
+  int dest = c;
+  uint32_t bad = 0;
+  int dir = 0;
+  if (own) {
+    const double F[3] = {o.fx, o.fy, o.fz};
+    double vf[3];
+    advance<SCALE>(g, F, o.x, o.v, first, lam, s_old, vf, vh, xn, dest, dir, bad);
+    if (ENERGY) {
+      acc.k += 0.5 * add_rn(add_rn(mul_rn(vf[0], vf[0]), mul_rn(vf[1], vf[1])),
+                               mul_rn(vf[2], vf[2]));
+      acc.u += o.uh;
+      acc.w += o.wh;
+    }
+    if (COUNT) {
+      acc.cand += (unsigned long long)(o.total - 1);
+      acc.inr += o.pc;
+    }
+  }
+  if (bad) raise_error(ra.err, abort_flag, bad);
+  const bool ok = own && !bad;
+  const bool stay = ok && dest == c;
+  const unsigned long long sm = __ballot(stay);
+  const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(sm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)sm, 0u));
+  store_atom(ra, dst, abort_flag, stay, ok, rank, dest, xn, vh, own ? o.id : 0u);
   if (lane == 0) gptr(ra.ncnt[dst])[c] = (uint32_t)__popcll(sm);
+  acc.left += (unsigned)__popcll(__ballot(ok && dir == 1));
+  acc.right += (unsigned)__popcll(__ballot(ok && dir == 2));
+}
+
+// All cells of a block on one wave (plain steps): lane l holds atom l of the block's cells
+// taken in order (at most 64 atoms), with its force F; cell q of the block holds lanes
+// [P_q, P_q + n_q).  The same updates and stores as one p2_tail per cell.
+template <class T>
+__device__ void p2_tail_block(const RunArgs& ra, const BlockHdr& H, const ForceOut& o, const T* Fl, int fstride,
+                              int src, int s_old, int first, ItemAcc& acc, uint32_t* abort_flag) {
+  const DGeom& g = ra.g;
+  const int lane = __lane_id();
+  const int dst = src ^ 1;
+  int n[BZ], P[BZ + 1];
+  P[0] = 0;
+#pragma unroll
+  for (int q = 0; q < BZ; q++) {
+    n[q] = q < H.nb ? H.cnt[9 * (q + 1) + 4] : 0;
+    P[q + 1] = P[q] + n[q];
+  }
+  static_assert(BZ == 4, "the cell split below assumes four cells per block");
+  const int q = (lane >= P[1] ? 1 : 0) + (lane >= P[2] ? 1 : 0) + (lane >= P[3] ? 1 : 0);
+  const int pq = q == 0 ? 0 : (q == 1 ? P[1] : (q == 2 ? P[2] : P[3]));
+  const int c = H.nb_cell[9 * (q + 1) + 4];
+  const bool own = lane < P[BZ];
+  double xn[3] = {0, 0, 0}, vh[3] = {0, 0, 0};
+  int dest = c;
+  uint32_t bad = 0;
+  int dir = 0;
+  if (own) {
+    // force of atom lane - pq of cell q, left in LDS by wave q
+    const T* fq = Fl + q * fstride + lane - pq;
+    const double F[3] = {(double)fq[0], (double)fq[64], (double)fq[128]};
+    double vf[3];
+    advance<false>(g, F, o.x, o.v, first, 1.0, s_old, vf, vh, xn, dest, dir, bad);
+  }
+  if (bad) raise_error(ra.err, abort_flag, bad);
+  const bool ok = own && !bad;
+  const bool stay = ok && dest == c;
+  const unsigned long long sm = __ballot(stay);
+  // rank among the stayers of the lane's own cell: stayers below the lane minus those below
+  // the cell's first lane
+  const unsigned long long below_cell = pq == 0 ? 0ull : (sm & ((1ull << pq) - 1ull));
+  const int rank =
+      (int)__builtin_amdgcn_mbcnt_hi((unsigned)(sm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)sm, 0u)) -
+      __popcll(below_cell);
+  store_atom(ra, dst, abort_flag, stay, ok, rank, dest, xn, vh, own ? o.id : 0u);
+  if (lane < H.nb) {
+    // stayers of cell lane: the new count of its own slots
+    const int pl = lane == 0 ? 0 : (lane == 1 ? P[1] : (lane == 2 ? P[2] : P[3]));
+    const int nl = lane == 0 ? n[0] : (lane == 1 ? n[1] : (lane == 2 ? n[2] : n[3]));
+    const unsigned long long seg = nl == 0 ? 0ull : ((nl == 64 ? ~0ull : ((1ull << nl) - 1ull)) << pl);
+    gptr(ra.ncnt[dst])[H.nb_cell[9 * (lane + 1) + 4]] = (uint32_t)__popcll(sm & seg);
+  }
   acc.left += (unsigned)__popcll(__ballot(ok && dir == 1));
   acc.right += (unsigned)__popcll(__ballot(ok && dir == 2));
 }
@@ -1252,10 +1381,17 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L
   const int e = (int)((long long)ra.g.cps * (it.chunk + 1) / ra.nch);
   ItemAcc acc;
   acc_zero(acc);
-  for_blocks<PREC, ENERGY, COUNT, true>(ra.g, ra.cells[src], ra.ncnt[src], it.slice, b, e, L, [&](const ForceOut& o) {
-    if (NVT) p2_force_tail<ENERGY, COUNT>(ra, o, src, first, acc);
-    else p2_tail<ENERGY, COUNT, false>(ra, o, src, it.slice, first, acc, abort_flag, 1.0);
-  });
+  // plain steps finish a block on one wave; energy, count and thermostat steps per wave
+  constexpr bool BTAIL = !ENERGY && !COUNT && !NVT;
+  for_blocks<PREC, ENERGY, COUNT, true, BTAIL>(
+      ra.g, ra.cells[src], ra.ncnt[src], it.slice, b, e, L,
+      [&](const ForceOut& o) {
+        if (NVT) p2_force_tail<ENERGY, COUNT>(ra, o, src, first, acc);
+        else p2_tail<ENERGY, COUNT, false>(ra, o, src, it.slice, first, acc, abort_flag, 1.0);
+      },
+      [&](const BlockHdr& H, const ForceOut& o, const auto* Fl, int fstride) {
+        p2_tail_block(ra, H, o, Fl, fstride, src, it.slice, first, acc, abort_flag);
+      });
   // wave reductions (fixed butterfly), then waves in order
   double u = acc.u, w = acc.w, k = acc.k, kt = acc.kt;
   unsigned long long cc = acc.cand, pc = acc.inr, nt = acc.nt;
@@ -1796,7 +1932,7 @@ __global__ __launch_bounds__(WG) void sync_kernel(DGeom g, const unsigned char* 
   const int slice = blockIdx.x / per_slice;
   const int b = (blockIdx.x % per_slice) * SYNC_CELLS;
   const int e = min(g.cps, b + SYNC_CELLS);
-  for_blocks<PREC, true, false, false>(g, cells, ncnt, slice, b, e, L, [&](const ForceOut& o) {
+  for_blocks<PREC, true, false, false, false>(g, cells, ncnt, slice, b, e, L, [&](const ForceOut& o) {
     if (o.c >= 0 && lane < o.n) {
       const gdouble* ib = cblk(cells, o.c);
       const uint32_t id = cids(ib)[lane];
@@ -1815,7 +1951,7 @@ __global__ __launch_bounds__(WG) void sync_kernel(DGeom g, const unsigned char* 
       u += o.uh;
       w += o.wh;
     }
-  });
+  }, [](const BlockHdr&, const ForceOut&, const auto*, int) {});
   for (int off = 32; off >= 1; off >>= 1) {
     u += __shfl_xor(u, off);
     w += __shfl_xor(w, off);
