@@ -260,7 +260,7 @@ int md_claim_table(int slices, int order, uint64_t seed, uint16_t *out);
 int md_wavefront_table(int slices, int levels, uint32_t *out);
 
 /* Device bytes a served run of this system holds at most (the admission measure): two
- * cell buffers of 3328 B per cell, cell and slice counters, the larger of the load copies
+ * cell buffers of 4352 B per cell, cell and slice counters, the larger of the load copies
  * and the read-back outputs (72 B per atom), the read-back energy partials, and the launch
  * scratch of one 64-step packed launch with the served work items, a quarter of a slice
  * of 32 to 64 cells each (work queue, energy partials, migration log).  -1 for an invalid

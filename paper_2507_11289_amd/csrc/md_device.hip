@@ -57,6 +57,15 @@ __device__ __forceinline__ guint32* cids(gdouble* b) {
 __device__ __forceinline__ const guint32* cids(const gdouble* b) {
   return (const guint32*)(b + CELL_DOUBLES);
 }
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef float vf3 __attribute__((ext_vector_type(3)));
+struct dpos {
+  double x, y, z;
+};
+typedef GLOBAL vf4 gvf4;
+// FP32 corner-relative positions (x, y, z, 0) of the slots
+__device__ __forceinline__ gvf4* crel(gdouble* b) { return (gvf4*)(cids(b) + CELL_CAP); }
+__device__ __forceinline__ const gvf4* crel(const gdouble* b) { return (const gvf4*)(cids(b) + CELL_CAP); }
 
 // FP64 sums, differences and products rounded one operation at a time, in the order
 // written, as the oracle computes them.  They are never fused into multiply-adds: this
@@ -103,6 +112,12 @@ __device__ __forceinline__ void raise_error(uint32_t* err, uint32_t* abort_flag,
 __device__ __forceinline__ int coord_cell(double x, double inv_l, int G) {
   const double f = floor(mul_rn(x, inv_l));
   return (int)fmin(fmax(f, 0.0), (double)(G - 1));
+}
+
+// Position x relative to the corner gc l of its cell, rounded once to FP32 (stored beside
+// the FP64 position for the FP32 pair path).
+__device__ __forceinline__ float corner_rel(double x, int gc, double l) {
+  return (float)sub_rn(x, mul_rn((double)gc, l));
 }
 
 // n / d for 0 <= n < 2^51 from inv = 1/d rounded to FP64: the quotient (n + 1/2) / d lies
@@ -193,6 +208,8 @@ constexpr int GMASKS = 4;  // pre-filter mask words kept per lane: one group of 
                            // guard-band pass (32 tiles)
 template <> struct BlockLDS<1> {  // FP32: positions relative to the block origin, |q|^2
   BlockHdr hb[2];                 // headers of the current and the next block
+  float4 qoff[2][BCELLS];         // per header: corner of staged cell m relative to the block
+                                  // origin, (k l) rounded to FP32 per axis
   float4 q[CAPB + QPAD];
   unsigned gmask[WAVES][GMASKS + 1][64];  // each wave's pass-1 marks of its current atom batch
                                          // (and a padding word read ahead, never used)
@@ -382,52 +399,40 @@ __device__ __forceinline__ float rel32(double x, int s, double L, double o) {
 
 // wrap: some staged cell of the block is a periodic image (its coordinates are shifted
 // by a box length); without it every shift is 0.
-template <int PREC>
-__device__ __forceinline__ void stage_put(const DGeom& g, const BlockHdr& H, BlockLDS<PREC>& L, const double o[3],
+// FP32: the staged coordinate is the atom's corner-relative FP32 position plus its staged
+// cell's corner relative to the block origin (qoff), one FP32 addition per axis.  The cell
+// indices of the corner are taken unwrapped, so a periodic image needs no shift.
+// FP64: raw positions for the exact FP64 pair terms, plus the image code and the FP32 |q|^2
+// the pre-filter rebuilds its FP32 coordinates from (x + s L) - o, rounded once.
+__device__ __forceinline__ void stage_put(const DGeom& g, const BlockHdr& H, BlockLDS<1>& L, const float4& off,
+                                          int m, int p, float rx, float ry, float rz) {
+  const float qx = rx + off.x, qy = ry + off.y, qz = rz + off.z;
+  // w: |q|^2, the norm term of the matrix-core distance test
+  L.q[p] = make_float4(qx, qy, qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+}
+__device__ __forceinline__ void stage_put(const DGeom& g, const BlockHdr& H, BlockLDS<0>& L, const double o[3],
                                           int m, int p, double x, double y, double z, bool wrap) {
-  if constexpr (PREC == 1) {
-    float qx, qy, qz;
-    if (!wrap) {
-      qx = (float)sub_rn(x, o[0]);
-      qy = (float)sub_rn(y, o[1]);
-      qz = (float)sub_rn(z, o[2]);
-    } else {
-      int nx, ny, nz;
-      staged_cell_xyz(H.gx, H.gy, H.z0, m, nx, ny, nz);
-      const double shx = nx < 0 ? -g.L[0] : (nx >= g.G[0] ? g.L[0] : 0.0);
-      const double shy = ny < 0 ? -g.L[1] : (ny >= g.G[1] ? g.L[1] : 0.0);
-      const double shz = nz < 0 ? -g.L[2] : (nz >= g.G[2] ? g.L[2] : 0.0);
-      qx = (float)sub_rn(add_rn(x, shx), o[0]);
-      qy = (float)sub_rn(add_rn(y, shy), o[1]);
-      qz = (float)sub_rn(add_rn(z, shz), o[2]);
-    }
-    // w: |q|^2, the norm term of the matrix-core distance test
-    L.q[p] = make_float4(qx, qy, qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
-  } else {
-    // raw positions for the exact FP64 pair terms; the image code and the FP32 |q|^2
-    // give the pre-filter the FP32 coordinates the FP32 staging would hold (without an
-    // image x + 0 L = x exactly, so both forms agree)
-    int sx = 0, sy = 0, sz = 0;
-    if (wrap) {
-      int nx, ny, nz;
-      staged_cell_xyz(H.gx, H.gy, H.z0, m, nx, ny, nz);
-      sx = nx < 0 ? -1 : (nx >= g.G[0] ? 1 : 0);
-      sy = ny < 0 ? -1 : (ny >= g.G[1] ? 1 : 0);
-      sz = nz < 0 ? -1 : (nz >= g.G[2] ? 1 : 0);
-    }
-    const float qx = rel32(x, sx, g.L[0], o[0]), qy = rel32(y, sy, g.L[1], o[1]), qz = rel32(z, sz, g.L[2], o[2]);
-    L.x[p] = x;
-    L.y[p] = y;
-    L.z[p] = z;
-    L.qn[p] = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
-    L.img[p] = (uint8_t)((sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4));
+  int sx = 0, sy = 0, sz = 0;
+  if (wrap) {
+    int nx, ny, nz;
+    staged_cell_xyz(H.gx, H.gy, H.z0, m, nx, ny, nz);
+    sx = nx < 0 ? -1 : (nx >= g.G[0] ? 1 : 0);
+    sy = ny < 0 ? -1 : (ny >= g.G[1] ? 1 : 0);
+    sz = nz < 0 ? -1 : (nz >= g.G[2] ? 1 : 0);
   }
+  const float qx = rel32(x, sx, g.L[0], o[0]), qy = rel32(y, sy, g.L[1], o[1]), qz = rel32(z, sz, g.L[2], o[2]);
+  L.x[p] = x;
+  L.y[p] = y;
+  L.z[p] = z;
+  L.qn[p] = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+  L.img[p] = (uint8_t)((sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4));
 }
 
 // Header of the block from the counts of hdr_issue: prefix, capacity check (the largest
 // nb whose 9 (nb + 2) cells fit; nb = 1 always fits).  One wave.
 template <int PREC>
-__device__ void hdr_commit(const DGeom& g, const StageRegs& R, BlockHdr& H) {
+__device__ void hdr_commit(const DGeom& g, const StageRegs& R, BlockLDS<PREC>& L, int hbi) {
+  BlockHdr& H = L.hb[hbi];
   const int lane = __lane_id();
   int incl = R.cnt;
 #pragma unroll
@@ -457,6 +462,18 @@ __device__ void hdr_commit(const DGeom& g, const StageRegs& R, BlockHdr& H) {
     const int nz = R.z0 - 1 + lane;
     H.wrap_layer[lane] = nz < 0 || nz >= g.G[2];
   }
+  if constexpr (PREC == 1) {
+    if (lane < BCELLS) {
+      // staged cell lane: x, y offsets -1..1 from the column, z from the aligned group start
+      // (the lane index is recomputed so that its conversions are not held across the block
+      // loop)
+      const int ln = opaque_tid() & 63;
+      const int r = ln % 9;
+      const int kx = r / 3 - 1, ky = r % 3 - 1, kz = ln / 9 - 1 + R.z0 % BZ;
+      L.qoff[hbi][ln] = make_float4((float)mul_rn((double)kx, g.l[0]), (float)mul_rn((double)ky, g.l[1]),
+                                    (float)mul_rn((double)kz, g.l[2]), 0.0f);
+    }
+  }
 }
 
 // Atoms of the block's own cells, in cell order (at most BZ cells).
@@ -473,8 +490,22 @@ __device__ __forceinline__ int block_atoms(const BlockHdr& H) {
 // issued after the staging loads, so the staging waits leave them in flight.  Whole
 // workgroup; the LDS entries must be free and H complete on entry; ends with a barrier.
 template <int PREC>
-__device__ void stage_fill(const DGeom& g, const unsigned char* cells, const BlockHdr& H, BlockLDS<PREC>& L,
-                           ForceOut& own, int own_mode, int tw) {
+__device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, BlockLDS<PREC>& L, ForceOut& own,
+                           int own_mode, int tw) {
+  const BlockHdr& H = L.hb[hbi];
+  // the staged position of a slot: FP32 corner-relative (FP32 pair path: x, y, z in one
+  // 12-byte load kept whole, so no register of it is reused, and nothing waits for the load,
+  // before the position is used) or FP64
+  typedef typename std::conditional<PREC == 1, vf3, dpos>::type PT;
+  auto load_pos = [&](const gdouble* jb, int k, PT& r) {
+    if constexpr (PREC == 1) {
+      r = *reinterpret_cast<const GLOBAL vf3*>(crel(jb) + k);
+    } else {
+      r.x = jb[k];
+      r.y = jb[CELL_CAP + k];
+      r.z = jb[2 * CELL_CAP + k];
+    }
+  };
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   const int nst = H.nst;
@@ -497,7 +528,7 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, const Blo
   const int m0 = tid >> 4, j = tid & 15;
   int pi[SROUNDS];  // staged entry of the lane's slot, or -1
   int ex[SROUNDS];  // the cell's atoms past its 16th (0 if none, or if not staged)
-  double x[SROUNDS], y[SROUNDS], z[SROUNDS];
+  PT r[SROUNDS];
   // raised wave priority while the loads are found and issued: the SIMD's other waves are
   // mostly in VALU-heavy pair loops, and an early issue lets the memory round trip overlap
   // their work
@@ -511,35 +542,27 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, const Blo
     const bool have = j < cnt;
     pi[i] = have ? H.pre[ms] + j : -1;
     ex[i] = max(cnt - 16, 0);
-    x[i] = y[i] = z[i] = 0.0;
-    if (have) {
-      const gdouble* jb = cblk(cells, cell);
-      x[i] = jb[j];
-      y[i] = jb[CELL_CAP + j];
-      z[i] = jb[2 * CELL_CAP + j];
-    }
+    r[i] = PT{0, 0, 0};
+    if (have) load_pos(cblk(cells, cell), j, r[i]);
   }
   // the slots past the 16th of the quarter's cells, concatenated: 16 of them per pass, the
   // first pass issued with the loads above
   static_assert(SROUNDS == 4, "the extra-slot split below assumes four rounds");
   const int e1 = ex[0], e2 = e1 + ex[1], e3 = e2 + ex[2], etot = e3 + ex[3];
-  auto extra = [&](int v, int& m, int& p, double& xv, double& yv, double& zv) {
+  auto extra = [&](int v, int& m, int& p, PT& rv) {
     const int i = (v >= e1 ? 1 : 0) + (v >= e2 ? 1 : 0) + (v >= e3 ? 1 : 0);
     const int k = 16 + v - (i == 0 ? 0 : (i == 1 ? e1 : (i == 2 ? e2 : e3)));
     m = m0 + 16 * i;
     p = -1;
-    xv = yv = zv = 0.0;
+    rv = PT{0, 0, 0};
     if (v < etot) {
-      const gdouble* jb = cblk(cells, H.nb_cell[m]);
       p = H.pre[m] + k;
-      xv = jb[k];
-      yv = jb[CELL_CAP + k];
-      zv = jb[2 * CELL_CAP + k];
+      load_pos(cblk(cells, H.nb_cell[m]), k, rv);
     }
   };
   int me, pe;
-  double xe, ye, ze;
-  extra(j, me, pe, xe, ye, ze);
+  PT re;
+  extra(j, me, pe, re);
   if (own_mode == 1 || (own_mode == 2 && w == tw)) {
     // own_mode 1: the wave's own cell (none if the capacity check dropped it); 2: cell q
     // of the block holds atoms [P_q, P_q + n_q) of the lanes
@@ -568,21 +591,27 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, const Blo
   }
   __builtin_amdgcn_s_setprio(0);
   double o[3];
-  block_origin(g, H.gx, H.gy, H.z0, o);
+  if constexpr (PREC == 0) block_origin(g, H.gx, H.gy, H.z0, o);
+  auto put = [&](int m, int p, const PT& rv) {
+    if constexpr (PREC == 1)
+      stage_put(g, H, L, L.qoff[hbi][m], m, p, rv.x, rv.y, rv.z);
+    else
+      stage_put(g, H, L, o, m, p, rv.x, rv.y, rv.z, wrap);
+  };
 #pragma unroll
   for (int i = 0; i < SROUNDS; i++)
-    if (pi[i] >= 0) stage_put<PREC>(g, H, L, o, m0 + 16 * i, pi[i], x[i], y[i], z[i], wrap);
-  if (pe >= 0) stage_put<PREC>(g, H, L, o, me, pe, xe, ye, ze, wrap);
+    if (pi[i] >= 0) put(m0 + 16 * i, pi[i], r[i]);
+  if (pe >= 0) put(me, pe, re);
   // every round's registers are read on every path: otherwise a load whose value is (in
   // the compiler's view) left unread looks outstanding later, and a later wait for other
   // loads also waits for it
 #pragma unroll
-  for (int i = 0; i < SROUNDS; i++) asm volatile("" ::"v"(x[i]), "v"(y[i]), "v"(z[i]));
-  asm volatile("" ::"v"(xe), "v"(ye), "v"(ze));
+  for (int i = 0; i < SROUNDS; i++) asm volatile("" ::"v"(r[i].x), "v"(r[i].y), "v"(r[i].z));
+  asm volatile("" ::"v"(re.x), "v"(re.y), "v"(re.z));
   // more than 16 extra slots in some quarter (dense cells): the rest, a pass at a time
   for (int v0 = 16; __ballot(v0 < etot); v0 += 16) {
-    extra(v0 + j, me, pe, xe, ye, ze);
-    if (pe >= 0) stage_put<PREC>(g, H, L, o, me, pe, xe, ye, ze, wrap);
+    extra(v0 + j, me, pe, re);
+    if (pe >= 0) put(me, pe, re);
   }
   __syncthreads();
 }
@@ -990,7 +1019,7 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
   int x = b, hb = 0, nblk = 0;
   if (w == 0) {
     issue(x, R);
-    hdr_commit<PREC>(g, R, L.hb[0]);
+    hdr_commit<PREC>(g, R, L, 0);
   }
   while (true) {
     __syncthreads();  // every wave is done with the previous block's LDS; header hb is complete
@@ -998,7 +1027,7 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
     const int tw = nblk & (WAVES - 1);
     const bool one = BTAIL && block_atoms(H) <= 64;
     ForceOut o;
-    stage_fill<PREC>(g, cells, H, L, o, OWN ? (one ? 2 : 1) : 0, tw);
+    stage_fill<PREC>(g, cells, hb, L, o, OWN ? (one ? 2 : 1) : 0, tw);
     block_force<PREC, ENERGY, COUNT>(g, cells, H, L, o);
     if (OWN) {
       // the pair loop has covered the own cell's loads; from here on their values count
@@ -1028,7 +1057,7 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
     if (!more) break;
     // the other header is free: every wave finished the block that used it before the
     // barrier above
-    if (w == 0) hdr_commit<PREC>(g, R, L.hb[hb ^ 1]);
+    if (w == 0) hdr_commit<PREC>(g, R, L, hb ^ 1);
     hb ^= 1;
     nblk++;
   }
@@ -1060,18 +1089,18 @@ __device__ __forceinline__ void acc_zero(ItemAcc& a) {
 // the left or right neighbour slice.
 // ---------------------------------------------------------------------------
 // The update of one atom: v(t) (vf), v(t + dt/2) (vh), the wrapped r(t + dt) (xn), its
-// cell (dest) and slice move (dir: 0 none, 1 left, 2 right); error bits in bad.
+// cell coordinates (gc) and index (dest), slice move (dir: 0 none, 1 left, 2 right); error
+// bits in bad.
 // SCALE: the thermostat factor lam multiplies v(t) first.
 template <bool SCALE>
 __device__ __forceinline__ void advance(const DGeom& g, const double F[3], const double x[3], const double v[3],
                                         int first, double lam, int s_old, double vf[3], double vh[3],
-                                        double xn[3], int& dest, int& dir, uint32_t& bad) {
+                                        double xn[3], int gc[3], int& dest, int& dir, uint32_t& bad) {
 #pragma unroll
   for (int d = 0; d < 3; d++) {
     vf[d] = first ? v[d] : add_rn(v[d], mul_rn(g.hdt, F[d]));
     if (SCALE) vf[d] = mul_rn(lam, vf[d]);
   }
-  int gc[3];
 #pragma unroll
   for (int d = 0; d < 3; d++) {
     vh[d] = add_rn(vf[d], mul_rn(g.hdt, F[d]));
@@ -1093,9 +1122,10 @@ __device__ __forceinline__ void advance(const DGeom& g, const double F[3], const
 
 // Store of one updated atom: a stayer at its rank among the cell's stayers (id order
 // kept), a mover appended from the top slot of its new cell.
+template <int PREC>
 __device__ __forceinline__ void store_atom(const RunArgs& ra, int dst, uint32_t* abort_flag, bool stay, bool ok,
-                                           int rank, int dest, const double xn[3], const double vh[3],
-                                           uint32_t id) {
+                                           int rank, int dest, const double xn[3], const int gc[3],
+                                           const double vh[3], uint32_t id) {
   int slot = -1;
   if (stay) {
     slot = rank;
@@ -1112,13 +1142,17 @@ __device__ __forceinline__ void store_atom(const RunArgs& ra, int dst, uint32_t*
       ob[d * CELL_CAP + slot] = xn[d];
       ob[(3 + d) * CELL_CAP + slot] = vh[d];
     }
+    // the FP32 corner-relative copy only where the FP32 pair path reads it
+    if constexpr (PREC == 1)
+      crel(ob)[slot] = vf4{corner_rel(xn[0], gc[0], ra.g.l[0]), corner_rel(xn[1], gc[1], ra.g.l[1]),
+                           corner_rel(xn[2], gc[2], ra.g.l[2]), 0.0f};
     cids(ob)[slot] = id;
   }
 }
 
 // One cell per wave (lanes < o.n).  SCALE: the thermostat factor lam multiplies v(t)
 // first (the forces come from the thermostat's force pass; energies were sampled there).
-template <bool ENERGY, bool COUNT, bool SCALE>
+template <int PREC, bool ENERGY, bool COUNT, bool SCALE>
 __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old, int first, ItemAcc& acc,
                         uint32_t* abort_flag, double lam) {
   const DGeom& g = ra.g;
@@ -1132,13 +1166,14 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old
   }
   const bool own = lane < o.n;
   double xn[3] = {0, 0, 0}, vh[3] = {0, 0, 0};
+  int gc[3] = {0, 0, 0};
   int dest = c;
   uint32_t bad = 0;
   int dir = 0;
   if (own) {
     const double F[3] = {o.fx, o.fy, o.fz};
     double vf[3];
-    advance<SCALE>(g, F, o.x, o.v, first, lam, s_old, vf, vh, xn, dest, dir, bad);
+    advance<SCALE>(g, F, o.x, o.v, first, lam, s_old, vf, vh, xn, gc, dest, dir, bad);
     if (ENERGY) {
       acc.k += 0.5 * add_rn(add_rn(mul_rn(vf[0], vf[0]), mul_rn(vf[1], vf[1])),
                                mul_rn(vf[2], vf[2]));
@@ -1155,7 +1190,7 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old
   const bool stay = ok && dest == c;
   const unsigned long long sm = __ballot(stay);
   const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(sm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)sm, 0u));
-  store_atom(ra, dst, abort_flag, stay, ok, rank, dest, xn, vh, own ? o.id : 0u);
+  store_atom<PREC>(ra, dst, abort_flag, stay, ok, rank, dest, xn, gc, vh, own ? o.id : 0u);
   if (lane == 0) gptr(ra.ncnt[dst])[c] = (uint32_t)__popcll(sm);
   acc.left += (unsigned)__popcll(__ballot(ok && dir == 1));
   acc.right += (unsigned)__popcll(__ballot(ok && dir == 2));
@@ -1164,7 +1199,7 @@ __device__ void p2_tail(const RunArgs& ra, const ForceOut& o, int src, int s_old
 // All cells of a block on one wave (plain steps): lane l holds atom l of the block's cells
 // taken in order (at most 64 atoms), with its force F; cell q of the block holds lanes
 // [P_q, P_q + n_q).  The same updates and stores as one p2_tail per cell.
-template <class T>
+template <int PREC, class T>
 __device__ void p2_tail_block(const RunArgs& ra, const BlockHdr& H, const ForceOut& o, const T* Fl, int fstride,
                               int src, int s_old, int first, ItemAcc& acc, uint32_t* abort_flag) {
   const DGeom& g = ra.g;
@@ -1183,6 +1218,7 @@ __device__ void p2_tail_block(const RunArgs& ra, const BlockHdr& H, const ForceO
   const int c = H.nb_cell[9 * (q + 1) + 4];
   const bool own = lane < P[BZ];
   double xn[3] = {0, 0, 0}, vh[3] = {0, 0, 0};
+  int gc[3] = {0, 0, 0};
   int dest = c;
   uint32_t bad = 0;
   int dir = 0;
@@ -1191,7 +1227,7 @@ __device__ void p2_tail_block(const RunArgs& ra, const BlockHdr& H, const ForceO
     const T* fq = Fl + q * fstride + lane - pq;
     const double F[3] = {(double)fq[0], (double)fq[64], (double)fq[128]};
     double vf[3];
-    advance<false>(g, F, o.x, o.v, first, 1.0, s_old, vf, vh, xn, dest, dir, bad);
+    advance<false>(g, F, o.x, o.v, first, 1.0, s_old, vf, vh, xn, gc, dest, dir, bad);
   }
   if (bad) raise_error(ra.err, abort_flag, bad);
   const bool ok = own && !bad;
@@ -1203,7 +1239,7 @@ __device__ void p2_tail_block(const RunArgs& ra, const BlockHdr& H, const ForceO
   const int rank =
       (int)__builtin_amdgcn_mbcnt_hi((unsigned)(sm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)sm, 0u)) -
       __popcll(below_cell);
-  store_atom(ra, dst, abort_flag, stay, ok, rank, dest, xn, vh, own ? o.id : 0u);
+  store_atom<PREC>(ra, dst, abort_flag, stay, ok, rank, dest, xn, gc, vh, own ? o.id : 0u);
   if (lane < H.nb) {
     // stayers of cell lane: the new count of its own slots
     const int pl = lane == 0 ? 0 : (lane == 1 ? P[1] : (lane == 2 ? P[2] : P[3]));
@@ -1264,10 +1300,12 @@ __device__ void cell_sort_wave(unsigned char* cells, int c, int n_low, int n_hig
   const bool act = lane < n;
   const int from = lane < n_low ? lane : CELL_CAP - 1 - (lane - n_low);
   double v[6];
+  vf4 r = {0.0f, 0.0f, 0.0f, 0.0f};
   uint32_t id = 0xffffffffu;
   if (act) {
 #pragma unroll
     for (int d = 0; d < 6; d++) v[d] = p[d * CELL_CAP + from];
+    r = crel(p)[from];
     id = ids[from];
   }
   int rank = 0;
@@ -1280,6 +1318,7 @@ __device__ void cell_sort_wave(unsigned char* cells, int c, int n_low, int n_hig
   if (act) {
 #pragma unroll
     for (int d = 0; d < 6; d++) p[d * CELL_CAP + rank] = v[d];
+    crel(p)[rank] = r;
     ids[rank] = id;
   }
 }
@@ -1387,10 +1426,10 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L
       ra.g, ra.cells[src], ra.ncnt[src], it.slice, b, e, L,
       [&](const ForceOut& o) {
         if (NVT) p2_force_tail<ENERGY, COUNT>(ra, o, src, first, acc);
-        else p2_tail<ENERGY, COUNT, false>(ra, o, src, it.slice, first, acc, abort_flag, 1.0);
+        else p2_tail<PREC, ENERGY, COUNT, false>(ra, o, src, it.slice, first, acc, abort_flag, 1.0);
       },
       [&](const BlockHdr& H, const ForceOut& o, const auto* Fl, int fstride) {
-        p2_tail_block(ra, H, o, Fl, fstride, src, it.slice, first, acc, abort_flag);
+        p2_tail_block<PREC>(ra, H, o, Fl, fstride, src, it.slice, first, acc, abort_flag);
       });
   // wave reductions (fixed butterfly), then waves in order
   double u = acc.u, w = acc.w, k = acc.k, kt = acc.kt;
@@ -1475,6 +1514,7 @@ __device__ void run_p2_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& L
 // Integrate item of a thermostat step (kernels md_thermo_b, md_v3b): the slice's scale
 // factor from the kinetic energy of all its force items (summed in chunk order), then
 // the velocity-Verlet update with v(t) scaled, and migration, cell by cell.
+template <int PREC>
 __device__ void run_p2b_item(const RunArgs& ra, const Item& it, double* s_lam, unsigned long long (*s_cnt)[5],
                              uint32_t* abort_flag) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1518,7 +1558,7 @@ __device__ void run_p2b_item(const RunArgs& ra, const Item& it, double* s_lam, u
       }
       o.id = cids(ib)[lane];
     }
-    p2_tail<false, false, true>(ra, o, src, it.slice, first, acc, abort_flag, lam);
+    p2_tail<PREC, false, false, true>(ra, o, src, it.slice, first, acc, abort_flag, lam);
   }
   if (lane == 0) {
     s_cnt[wave][0] = acc.left;
@@ -1578,7 +1618,7 @@ __device__ void run_item(const RunArgs& ra, const Item& it, BlockLDS<PREC>& ws, 
       else run_p2_item<PREC, false, false, false>(ra, it, ws, s_red, s_cnt, ra.abort);
     }
   } else if (NVT && it.phase == 2) {
-    run_p2b_item(ra, it, &s_red[0][0], s_cnt, ra.abort);
+    run_p2b_item<PREC>(ra, it, &s_red[0][0], s_cnt, ra.abort);
   } else {
     const int dst = (ra.par0 + it.k + 1) & 1;
     const int b = (int)((long long)ra.g.cps * it.chunk / ra.nchA);
@@ -1893,6 +1933,8 @@ __global__ void load_scatter_kernel(DGeom g, const double* pos, const double* ve
         b[d * CELL_CAP + slot] = pos[3 * i + d];
         b[(3 + d) * CELL_CAP + slot] = vel[3 * i + d];
       }
+      crel(b)[slot] = vf4{corner_rel(pos[3 * i], gc[0], g.l[0]), corner_rel(pos[3 * i + 1], gc[1], g.l[1]),
+                          corner_rel(pos[3 * i + 2], gc[2], g.l[2]), 0.0f};
       cids(b)[slot] = (uint32_t)i;
     } else {
       atomicOr(err, ERR_CAPACITY);

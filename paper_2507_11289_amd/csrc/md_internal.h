@@ -2,7 +2,10 @@
 //
 // Data layout in HBM (one simulation or one served run):
 //   two cell buffers (parity 0/1).  A cell owns CELL_CAP atom slots stored as one
-//   block: x[64] y[64] z[64] vx[64] vy[64] vz[64] (FP64) then id[64] (u32).
+//   block: x[64] y[64] z[64] vx[64] vy[64] vz[64] (FP64), id[64] (u32), then
+//   r[64] (FP32 x, y, z, 0): the position relative to the cell's corner, x - gx l rounded
+//   once (the FP32 pair path stages these: one 16-byte load per atom, two cache lines for
+//   16 atoms instead of three).
 //   Cells are numbered slice-major: cell = slice * cells_per_slice +
 //   ((gx mod ncx) * Gy + gy) * Gz + gz, so a slice is one contiguous range of blocks.
 //   ncnt[p][cell]: atoms in the cell; nin[p][cell]: atoms that moved in from
@@ -15,7 +18,7 @@ namespace mdk {
 
 constexpr int CELL_CAP = 64;                 // slots per cell (one wavefront)
 constexpr int CELL_DOUBLES = 6 * CELL_CAP;   // x y z vx vy vz
-constexpr int CELL_BYTES = CELL_DOUBLES * 8 + CELL_CAP * 4;  // 3328
+constexpr int CELL_BYTES = CELL_DOUBLES * 8 + CELL_CAP * 4 + CELL_CAP * 16;  // 4352 = 17 x 256
 constexpr int WG = 256;                      // threads per workgroup (4 waves)
 constexpr int WAVES = WG / 64;
 constexpr int BLOCK_CELLS = WAVES;            // cells of one z-column per staged block (one per wave)

@@ -511,7 +511,7 @@ def test_torch_caching_allocator_gives_the_same_trajectory(c0):
             sim.step(10)
             got = sim.state()
             held = torch.cuda.memory_allocated() - base
-        assert held >= 2 * 3328 * (c0.slices * 25)
+        assert held >= 2 * 4352 * (c0.slices * 25)
         assert torch.cuda.memory_allocated() == base
     finally:
         md.set_allocator(None, None)
