@@ -487,8 +487,9 @@ __device__ __forceinline__ int block_atoms(const BlockHdr& H) {
 // Stage the block of header H into LDS.  own_mode 1: every wave also loads the position,
 // velocity and id of its own cell's atoms into own; 2: wave tw loads those of all the
 // block's cells, atom l of them (in cell order) on lane l (at most 64).  These loads are
-// issued after the staging loads, so the staging waits leave them in flight.  Whole
-// workgroup; the LDS entries must be free and H complete on entry; ends with a barrier.
+// issued last, once the staged entries are written, and arrive during the pair loops
+// (which wait for no memory operation).  Whole workgroup; the LDS entries must be free
+// and H complete on entry; ends with a barrier.
 template <int PREC>
 __device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, BlockLDS<PREC>& L, ForceOut& own,
                            int own_mode, int tw) {
@@ -563,6 +564,33 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, 
   int me, pe;
   PT re;
   extra(j, me, pe, re);
+  __builtin_amdgcn_s_setprio(0);
+  double o[3];
+  if constexpr (PREC == 0) block_origin(g, H.gx, H.gy, H.z0, o);
+  auto put = [&](int m, int p, const PT& rv) {
+    if constexpr (PREC == 1)
+      stage_put(g, H, L, L.qoff[hbi][m], m, p, rv.x, rv.y, rv.z);
+    else
+      stage_put(g, H, L, o, m, p, rv.x, rv.y, rv.z, wrap);
+  };
+#pragma unroll
+  for (int i = 0; i < SROUNDS; i++)
+    if (pi[i] >= 0) put(m0 + 16 * i, pi[i], r[i]);
+  if (pe >= 0) put(me, pe, re);
+  // every round's registers are read on every path: otherwise a load whose value is (in
+  // the compiler's view) left unread looks outstanding later, and a later wait for other
+  // loads also waits for it
+#pragma unroll
+  for (int i = 0; i < SROUNDS; i++) asm volatile("" ::"v"(r[i].x), "v"(r[i].y), "v"(r[i].z));
+  asm volatile("" ::"v"(re.x), "v"(re.y), "v"(re.z));
+  // more than 16 extra slots in some quarter (dense cells): the rest, a pass at a time
+  for (int v0 = 16; __ballot(v0 < etot); v0 += 16) {
+    extra(v0 + j, me, pe, re);
+    if (pe >= 0) put(me, pe, re);
+    // read on every path: a load left in flight here would make a later write of these
+    // registers wait for the memory counter (and with it for every later load)
+    asm volatile("" ::"v"(re.x), "v"(re.y), "v"(re.z));
+  }
   if (own_mode == 1 || (own_mode == 2 && w == tw)) {
     // own_mode 1: the wave's own cell (none if the capacity check dropped it); 2: cell q
     // of the block holds atoms [P_q, P_q + n_q) of the lanes
@@ -588,30 +616,6 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, 
       }
       own.id = cids(ib)[k];
     }
-  }
-  __builtin_amdgcn_s_setprio(0);
-  double o[3];
-  if constexpr (PREC == 0) block_origin(g, H.gx, H.gy, H.z0, o);
-  auto put = [&](int m, int p, const PT& rv) {
-    if constexpr (PREC == 1)
-      stage_put(g, H, L, L.qoff[hbi][m], m, p, rv.x, rv.y, rv.z);
-    else
-      stage_put(g, H, L, o, m, p, rv.x, rv.y, rv.z, wrap);
-  };
-#pragma unroll
-  for (int i = 0; i < SROUNDS; i++)
-    if (pi[i] >= 0) put(m0 + 16 * i, pi[i], r[i]);
-  if (pe >= 0) put(me, pe, re);
-  // every round's registers are read on every path: otherwise a load whose value is (in
-  // the compiler's view) left unread looks outstanding later, and a later wait for other
-  // loads also waits for it
-#pragma unroll
-  for (int i = 0; i < SROUNDS; i++) asm volatile("" ::"v"(r[i].x), "v"(r[i].y), "v"(r[i].z));
-  asm volatile("" ::"v"(re.x), "v"(re.y), "v"(re.z));
-  // more than 16 extra slots in some quarter (dense cells): the rest, a pass at a time
-  for (int v0 = 16; __ballot(v0 < etot); v0 += 16) {
-    extra(v0 + j, me, pe, re);
-    if (pe >= 0) put(me, pe, re);
   }
   __syncthreads();
 }
@@ -778,6 +782,11 @@ __device__ void block_force32(const DGeom& g, const unsigned char* cells, const 
             if (f < fe) guard(f);
           }
       }
+      // the own position is read on every path: a load of it left in flight (no band
+      // pair on this lane) would make the next pair loop wait for the memory counter before
+      // reusing its registers -- and that wait also covers the own-cell loads of the block,
+      // which are still in flight when the first pair loop starts
+      asm volatile("" ::"v"(xi), "v"(yi), "v"(zi));
     }
     // quarter partials of column col as (q0 + q1) + (q2 + q3), by two exchanges; IEEE
     // addition is commutative, so all four lanes of the column hold the same sum and lane
