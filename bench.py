@@ -55,19 +55,19 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11289_amd", "csrc", f)
 # the kernel sources have the hash they were taken on (profiles/persistent_f32_lean_lj_fluid_4m.md,
 # profiles/persistent_f64_lean_lj_fluid_4m.md); otherwise null.
 COUNTERS = {
-    "source_sha256": "2f7a22a760b21149b61eab2185861220ffd617e8079cb230794ca533d76877ab",
+    "source_sha256": "2d88c2551842ca71a4624eecac53e6d9733def191b8f43b0938a75d365209b83",
     "workload": "lj_fluid_4m",
     "persistent_f32_lean": {
-        "hbm_read_bytes_per_atom_step": 253.8, "hbm_write_bytes_per_atom_step": 80.7,
+        "hbm_read_bytes_per_atom_step": 254.3, "hbm_write_bytes_per_atom_step": 80.7,
         "valu_fp32_flop_per_atom_step": 2354.7, "valu_fp64_flop_per_atom_step": 54.5,
         "mfma_f32_flop_per_atom_step": 3773.2, "valu_instructions_per_cell_step": 1128.0,
-        "valu_pipe_busy": 0.695, "l2_hit_rate": 0.361, "lds_conflict_cycles_per_lds_cycle": 1.648,
+        "valu_pipe_busy": 0.723, "l2_hit_rate": 0.36, "lds_conflict_cycles_per_lds_cycle": 1.639,
         "profile": "profiles/persistent_f32_lean_lj_fluid_4m.md"},
     "persistent_f64_lean": {
-        "hbm_read_bytes_per_atom_step": 312.9, "hbm_write_bytes_per_atom_step": 65.2,
+        "hbm_read_bytes_per_atom_step": 313.0, "hbm_write_bytes_per_atom_step": 65.2,
         "valu_fp32_flop_per_atom_step": 107.1, "valu_fp64_flop_per_atom_step": 3656.8,
         "mfma_f32_flop_per_atom_step": 3773.2, "valu_instructions_per_cell_step": 1708.0,
-        "valu_pipe_busy": 0.565, "l2_hit_rate": 0.393, "lds_conflict_cycles_per_lds_cycle": 0.492,
+        "valu_pipe_busy": 0.571, "l2_hit_rate": 0.396, "lds_conflict_cycles_per_lds_cycle": 0.498,
         "profile": "profiles/persistent_f64_lean_lj_fluid_4m.md"},
 }
 
