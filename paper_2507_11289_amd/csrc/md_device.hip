@@ -330,14 +330,18 @@ __device__ __forceinline__ void pair64(const DGeom& g, double xi, double yi, dou
 //     counts arrive while the previous block is integrated;
 //   hdr_commit: prefix of the counts, capacity check, header (double-buffered, so the
 //     next block's header is written while the current one is in use).
-// Then the whole workgroup stages the block (stage_fill): each quarter wave (16 lanes)
-// takes whole staged cells, one atom slot per lane: cell 16 i + 4 w + quarter of wave w
-// for i < SROUNDS, all of them loaded at once (one memory round trip for the whole
-// block), then written into LDS at the cell's place in the compact staged list.  The
-// slots past the 16th of a quarter's cells follow, concatenated, in one more batch.
+// Then the staging waves (all four, or the three that are not finishing the previous
+// block) stage the block (stage_entries): each quarter wave (16 lanes) takes whole staged
+// cells, one atom slot per lane: cell NQ i + 4 s + quarter of staging wave s for i < SR
+// (NQ = 4 x staging waves), all of them loaded at once (one memory round trip for the
+// whole block), then written into LDS at the cell's place in the compact staged list.
+// The slots past the 16th of a quarter's cells follow, concatenated, in one more batch.
 // ---------------------------------------------------------------------------
-constexpr int SROUNDS = (BCELLS + 15) / 16;  // staged cells per quarter wave
-static_assert(16 * SROUNDS <= 64, "a staged cell index must name a lane of the wave");
+template <int NSW> struct StageShape {
+  static constexpr int NQ = 4 * NSW;                 // quarter waves staging
+  static constexpr int SR = (BCELLS + NQ - 1) / NQ;  // staged cells per quarter wave
+  static_assert(NQ * SR <= 64, "a staged cell index must name a lane of the wave");
+};
 
 // threadIdx.x behind an empty asm: index arithmetic derived from it stays where it is
 // used instead of being hoisted out of the block loop and held in registers through the
@@ -484,15 +488,12 @@ __device__ __forceinline__ int block_atoms(const BlockHdr& H) {
   return t;
 }
 
-// Stage the block of header H into LDS.  own_mode 1: every wave also loads the position,
-// velocity and id of its own cell's atoms into own; 2: wave tw loads those of all the
-// block's cells, atom l of them (in cell order) on lane l (at most 64).  These loads are
-// issued last, once the staged entries are written, and arrive during the pair loops
-// (which wait for no memory operation).  Whole workgroup; the LDS entries must be free
-// and H complete on entry; ends with a barrier.
-template <int PREC>
-__device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, BlockLDS<PREC>& L, ForceOut& own,
-                           int own_mode, int tw) {
+// Stage the block of header hbi into LDS with NSW waves; the calling wave is staging wave
+// sw (0 .. NSW - 1).  The LDS entries must be free and the header complete on entry; no
+// barrier.
+template <int PREC, int NSW>
+__device__ void stage_entries(const DGeom& g, const unsigned char* cells, int hbi, BlockLDS<PREC>& L, int sw) {
+  constexpr int NQ = StageShape<NSW>::NQ, SR = StageShape<NSW>::SR;
   const BlockHdr& H = L.hb[hbi];
   // the staged position of a slot: FP32 corner-relative (FP32 pair path: x, y, z in one
   // 12-byte load kept whole, so no register of it is reused, and nothing waits for the load,
@@ -508,10 +509,9 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, 
     }
   };
   const int lane = __lane_id();
-  const int w = threadIdx.x >> 6;
   const int nst = H.nst;
   const bool wrap = H.wrap;
-  if (w == 0 && lane < QPAD) {
+  if (sw == 0 && lane < QPAD) {
     // far sentinels after the last staged atom: a pair-loop read past the end of the
     // list finds no partner in range
     const int stot = H.pre[nst];
@@ -523,20 +523,20 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, 
       L.img[stot + lane] = IMG_NONE;
     }
   }
-  // staged cell of round 0 (round i: m0 + 16 i), i.e. 4 w + quarter; recomputed here so
+  // staged cell of round 0 (round i: m0 + NQ i), i.e. 4 sw + quarter; recomputed here so
   // that the per-round indices are not hoisted out of the block loop and held in registers
-  const int tid = opaque_tid();
-  const int m0 = tid >> 4, j = tid & 15;
-  int pi[SROUNDS];  // staged entry of the lane's slot, or -1
-  int ex[SROUNDS];  // the cell's atoms past its 16th (0 if none, or if not staged)
-  PT r[SROUNDS];
+  const int st = NSW == WAVES ? opaque_tid() : ((sw << 6) | (opaque_tid() & 63));
+  const int m0 = st >> 4, j = st & 15;
+  int pi[SR];  // staged entry of the lane's slot, or -1
+  int ex[SR];  // the cell's atoms past its 16th (0 if none, or if not staged)
+  PT r[SR];
   // raised wave priority while the loads are found and issued: the SIMD's other waves are
   // mostly in VALU-heavy pair loops, and an early issue lets the memory round trip overlap
   // their work
   __builtin_amdgcn_s_setprio(2);
 #pragma unroll
-  for (int i = 0; i < SROUNDS; i++) {
-    const int m = m0 + 16 * i;
+  for (int i = 0; i < SR; i++) {
+    const int m = m0 + NQ * i;
     const int ms = m < BCELLS ? m : 0;
     const int cnt = m < nst ? H.cnt[ms] : 0;
     const int cell = H.nb_cell[ms];
@@ -547,13 +547,22 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, 
     if (have) load_pos(cblk(cells, cell), j, r[i]);
   }
   // the slots past the 16th of the quarter's cells, concatenated: 16 of them per pass, the
-  // first pass issued with the loads above
-  static_assert(SROUNDS == 4, "the extra-slot split below assumes four rounds");
-  const int e1 = ex[0], e2 = e1 + ex[1], e3 = e2 + ex[2], etot = e3 + ex[3];
+  // first pass issued with the loads above; ec[i] = extra slots of the rounds before i
+  int ec[SR + 1];
+  ec[0] = 0;
+#pragma unroll
+  for (int i = 0; i < SR; i++) ec[i + 1] = ec[i] + ex[i];
+  const int etot = ec[SR];
   auto extra = [&](int v, int& m, int& p, PT& rv) {
-    const int i = (v >= e1 ? 1 : 0) + (v >= e2 ? 1 : 0) + (v >= e3 ? 1 : 0);
-    const int k = 16 + v - (i == 0 ? 0 : (i == 1 ? e1 : (i == 2 ? e2 : e3)));
-    m = m0 + 16 * i;
+    int i = 0, base = 0;
+#pragma unroll
+    for (int t = 1; t < SR; t++)
+      if (v >= ec[t]) {
+        i = t;
+        base = ec[t];
+      }
+    const int k = 16 + v - base;
+    m = m0 + NQ * i;
     p = -1;
     rv = PT{0, 0, 0};
     if (v < etot) {
@@ -574,14 +583,14 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, 
       stage_put(g, H, L, o, m, p, rv.x, rv.y, rv.z, wrap);
   };
 #pragma unroll
-  for (int i = 0; i < SROUNDS; i++)
-    if (pi[i] >= 0) put(m0 + 16 * i, pi[i], r[i]);
+  for (int i = 0; i < SR; i++)
+    if (pi[i] >= 0) put(m0 + NQ * i, pi[i], r[i]);
   if (pe >= 0) put(me, pe, re);
   // every round's registers are read on every path: otherwise a load whose value is (in
   // the compiler's view) left unread looks outstanding later, and a later wait for other
   // loads also waits for it
 #pragma unroll
-  for (int i = 0; i < SROUNDS; i++) asm volatile("" ::"v"(r[i].x), "v"(r[i].y), "v"(r[i].z));
+  for (int i = 0; i < SR; i++) asm volatile("" ::"v"(r[i].x), "v"(r[i].y), "v"(r[i].z));
   asm volatile("" ::"v"(re.x), "v"(re.y), "v"(re.z));
   // more than 16 extra slots in some quarter (dense cells): the rest, a pass at a time
   for (int v0 = 16; __ballot(v0 < etot); v0 += 16) {
@@ -591,9 +600,18 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, 
     // registers wait for the memory counter (and with it for every later load)
     asm volatile("" ::"v"(re.x), "v"(re.y), "v"(re.z));
   }
+}
+
+// Position, velocity and id of own atoms of the block of header H into own.  own_mode 1:
+// every wave loads those of its own cell (none if the capacity check dropped it); 2: wave
+// tw loads those of all the block's cells, atom l of them (in cell order) on lane l (at
+// most 64).  The pair loops wait for no memory operation, so the loads arrive during them.
+__device__ __forceinline__ void own_load(const unsigned char* cells, const BlockHdr& H, ForceOut& own, int own_mode,
+                                         int tw) {
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
   if (own_mode == 1 || (own_mode == 2 && w == tw)) {
-    // own_mode 1: the wave's own cell (none if the capacity check dropped it); 2: cell q
-    // of the block holds atoms [P_q, P_q + n_q) of the lanes
+    // own_mode 2: cell q of the block holds atoms [P_q, P_q + n_q) of the lanes
     int q = w, k = lane, nq = w < H.nb ? H.cnt[9 * (w + 1) + 4] : 0;
     if (own_mode == 2) {
       int nr[BZ], P[BZ + 1];
@@ -617,6 +635,17 @@ __device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, 
       own.id = cids(ib)[k];
     }
   }
+}
+
+// Stage the block of header hbi into LDS with all waves, then (own_mode 1 or 2) the own
+// atoms' loads of own_load, issued last, once the staged entries are written.  Whole
+// workgroup; the LDS entries must be free and the header complete on entry; ends with a
+// barrier.
+template <int PREC>
+__device__ void stage_fill(const DGeom& g, const unsigned char* cells, int hbi, BlockLDS<PREC>& L, ForceOut& own,
+                           int own_mode, int tw) {
+  stage_entries<PREC, WAVES>(g, cells, hbi, L, threadIdx.x >> 6);
+  own_load(cells, L.hb[hbi], own, own_mode, tw);
   __syncthreads();
 }
 
@@ -1008,7 +1037,8 @@ static_assert(sizeof(double) * (CAPB + QPAD) >= sizeof(double) * WAVES * 3 * 64,
 // wave's own atoms are loaded with the staging and arrive during the pair loop.  With
 // BTAIL, a block whose cells hold at most 64 atoms is finished by one wave (taking turns
 // block by block): the waves leave their forces in LDS and fnb(H, o, forces, stride)
-// runs on that wave, whose lanes hold the block's atoms in cell order.  Whole workgroup.
+// runs on that wave, whose lanes hold the block's atoms in cell order; in FP32 the other
+// three waves stage the next block meanwhile (see the branch below).  Whole workgroup.
 template <int PREC, bool ENERGY, bool COUNT, bool OWN, bool BTAIL, class Fn, class FnB>
 __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uint32_t* ncnt, int slice, int b,
                            int e, BlockLDS<PREC>& L, Fn&& fn, FnB&& fnb) {
@@ -1029,6 +1059,54 @@ __device__ void for_blocks(const DGeom& g, const unsigned char* cells, const uin
   if (w == 0) {
     issue(x, R);
     hdr_commit<PREC>(g, R, L, 0);
+  }
+  if constexpr (PREC == 1 && OWN && BTAIL) {
+    // FP32 plain steps: the wave that finishes a block (tw, taking turns) integrates it
+    // while the three others stage the next block, so the integration runs under the
+    // staging's memory round trip.  The forces it reads are in the waves' mask words,
+    // which the staging does not touch.  Wave 0 writes the next block's header as soon as
+    // its pair loop is done, from counts loaded one block earlier (during the staging).
+    typedef BlockForces<PREC> BF;
+    ForceOut o;
+    __syncthreads();  // the first header is complete
+    if (w != WAVES - 1) stage_entries<PREC, WAVES - 1>(g, cells, 0, L, w);
+    if (w == 0 && x + L.hb[0].nb < e) issue(x + L.hb[0].nb, R);
+    while (true) {
+      __syncthreads();  // the block is staged; the previous block is finished
+      const BlockHdr& H = L.hb[hb];
+      const int tw = nblk & (WAVES - 1);
+      const bool one = block_atoms(H) <= 64;
+      own_load(cells, H, o, one ? 2 : 1, tw);
+      block_force<PREC, ENERGY, COUNT>(g, cells, H, L, o);
+      // the pair loop has covered the own atoms' loads; from here on their values count
+      // as plain registers, so the tail waits for no later load on their account
+      asm volatile("" : "+v"(o.id), "+v"(o.x[0]), "+v"(o.x[1]), "+v"(o.x[2]), "+v"(o.v[0]), "+v"(o.v[1]),
+                   "+v"(o.v[2]));
+      x += H.nb;
+      const bool more = x < e;
+      if (more && w == 0) hdr_commit<PREC>(g, R, L, hb ^ 1);
+      typename BF::T* Fl = BF::at(L);
+      if (one) {
+        const int lane = __lane_id();
+        if (lane < o.n) {
+          Fl[w * BF::FSTRIDE + lane] = o.fx;
+          Fl[w * BF::FSTRIDE + 64 + lane] = o.fy;
+          Fl[w * BF::FSTRIDE + 128 + lane] = o.fz;
+        }
+      }
+      __syncthreads();  // forces in LDS, staged entries free, next header complete
+      if (one) {
+        if (w == tw) fnb(H, o, (const typename BF::T*)Fl, BF::FSTRIDE);
+      } else {
+        fn(o);
+      }
+      if (!more) break;
+      if (w != tw) stage_entries<PREC, WAVES - 1>(g, cells, hb ^ 1, L, (w + WAVES - 1 - tw) & (WAVES - 1));
+      if (w == 0 && x + L.hb[hb ^ 1].nb < e) issue(x + L.hb[hb ^ 1].nb, R);
+      hb ^= 1;
+      nblk++;
+    }
+    return;
   }
   while (true) {
     __syncthreads();  // every wave is done with the previous block's LDS; header hb is complete
