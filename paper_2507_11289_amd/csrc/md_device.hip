@@ -1034,7 +1034,8 @@ static_assert(sizeof(double) * (CAPB + QPAD) >= sizeof(double) * WAVES * 3 * 64,
 // runs on every wave after each block's forces.  Wave 0 prepares the headers: the next
 // block's counts are loaded before fn and its header is written after it, while the
 // other waves wait for the next block.  With OWN, the position, velocity and id of the
-// wave's own atoms are loaded with the staging and arrive during the pair loop.  With
+// wave's own atoms are loaded with the staging (in the FP32 branch below, right after
+// it) and arrive during the pair loop.  With
 // BTAIL, a block whose cells hold at most 64 atoms is finished by one wave (taking turns
 // block by block): the waves leave their forces in LDS and fnb(H, o, forces, stride)
 // runs on that wave, whose lanes hold the block's atoms in cell order; in FP32 the other
