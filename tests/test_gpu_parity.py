@@ -308,16 +308,18 @@ def test_schedule_invariance_is_bitwise(medium, prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_block_integration_equals_per_wave_integration(medium, prec):
     """Plain steps finish each block on one wave (the waves leave their forces in LDS, one
-    wave advances the atoms of all the block's cells); steps with an energy sample integrate
-    each cell on its own wave.  Both give bitwise the same trajectory and binning: 15 plain
-    steps against 15 sampled ones, on the liquid and on a dense liquid (about 19 atoms per
-    cell), where many blocks hold more than 64 atoms and integrate per wave in both runs."""
+    wave advances the atoms of all the block's cells, in FP32 while the other waves stage
+    the next block); steps with an energy sample integrate each cell on its own wave.  All
+    give bitwise the same trajectory and binning: 15 plain steps against 15 sampled ones and
+    against a sample every third step (both kinds of step in one launch), on the liquid and
+    on a dense liquid (about 19 atoms per cell), where many blocks hold more than 64 atoms
+    and integrate per wave in every run."""
     box, pos, vel, _ = inputs.homogeneous(20000, 1.2, 1.5, 31)
     dense = inputs.System("dense", box, 4, pos, vel)
     for sysm in (medium, dense):
         say(f"[gpu] block vs per-wave integration, {sysm.name}, precision={prec}")
         outs = []
-        for every in (0, 1):
+        for every in (0, 1, 3):
             with md.Sim(sysm.box, sysm.slices, sysm.rc, sysm.dt, prec) as sim:
                 if every:
                     sim.set_option(md.OPT_ENERGY_EVERY, every)
@@ -325,8 +327,9 @@ def test_block_integration_equals_per_wave_integration(medium, prec):
                 sim.step(15)
                 p, v, _ = sim.state()
                 outs.append((p, v, sim.cells()))
-        for a, b in zip(outs[0], outs[1]):
-            assert np.array_equal(a, b)
+        for other in outs[1:]:
+            for a, b in zip(outs[0], other):
+                assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("prec", PRECS)
