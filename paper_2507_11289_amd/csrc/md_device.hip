@@ -1929,20 +1929,24 @@ __device__ __forceinline__ void persistent_body(const LaunchArgs& la) {
   }
 }
 
-// The plain FP32 kernel is held to 128 VGPRs (4 waves per SIMD) and the energy-sampling
-// ones to 168 (3 waves per SIMD; FP64 workgroups need that much LDS anyway); the
-// pair-counting (statistics) and thermostat kernels take what they need.
+// The FP32 kernels for plain launches, launches with energy samples and thermostat
+// launches are held to 128 VGPRs (4 waves per SIMD), the FP64 ones to 168 (3 waves per
+// SIMD; FP64 workgroups need that much LDS anyway): a launch runs all its steps in one
+// kernel, and the registers that a sampled or thermostat step would need beyond that are
+// spilled on those steps rather than lowering the occupancy of every step.  The
+// pair-counting (statistics) kernels and the thermostat kernels with energy samples take
+// what they need.
 #define MD_WPE(n) __attribute__((amdgpu_waves_per_eu(n)))
 __global__ __launch_bounds__(WG) MD_WPE(4) void persistent_f32_lean(LaunchArgs la) { persistent_body<1, 0, false>(la); }
-__global__ __launch_bounds__(WG) MD_WPE(3) void persistent_f32_energy(LaunchArgs la) { persistent_body<1, 1, false>(la); }
+__global__ __launch_bounds__(WG) MD_WPE(4) void persistent_f32_energy(LaunchArgs la) { persistent_body<1, 1, false>(la); }
 __global__ __launch_bounds__(WG) void persistent_f32_full(LaunchArgs la) { persistent_body<1, 2, false>(la); }
 __global__ __launch_bounds__(WG) MD_WPE(3) void persistent_f64_lean(LaunchArgs la) { persistent_body<0, 0, false>(la); }
 __global__ __launch_bounds__(WG) MD_WPE(3) void persistent_f64_energy(LaunchArgs la) { persistent_body<0, 1, false>(la); }
 __global__ __launch_bounds__(WG) void persistent_f64_full(LaunchArgs la) { persistent_body<0, 2, false>(la); }
-__global__ __launch_bounds__(WG) void persistent_f32_lean_nvt(LaunchArgs la) { persistent_body<1, 0, true>(la); }
+__global__ __launch_bounds__(WG) MD_WPE(4) void persistent_f32_lean_nvt(LaunchArgs la) { persistent_body<1, 0, true>(la); }
 __global__ __launch_bounds__(WG) void persistent_f32_energy_nvt(LaunchArgs la) { persistent_body<1, 1, true>(la); }
 __global__ __launch_bounds__(WG) void persistent_f32_full_nvt(LaunchArgs la) { persistent_body<1, 2, true>(la); }
-__global__ __launch_bounds__(WG) void persistent_f64_lean_nvt(LaunchArgs la) { persistent_body<0, 0, true>(la); }
+__global__ __launch_bounds__(WG) MD_WPE(3) void persistent_f64_lean_nvt(LaunchArgs la) { persistent_body<0, 0, true>(la); }
 __global__ __launch_bounds__(WG) void persistent_f64_energy_nvt(LaunchArgs la) { persistent_body<0, 1, true>(la); }
 __global__ __launch_bounds__(WG) void persistent_f64_full_nvt(LaunchArgs la) { persistent_body<0, 2, true>(la); }
 #undef MD_WPE
