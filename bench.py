@@ -55,16 +55,16 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11289_amd", "csrc", f)
 # the kernel sources have the hash they were taken on (profiles/persistent_f32_lean_lj_fluid_4m.md,
 # profiles/persistent_f64_lean_lj_fluid_4m.md); otherwise null.
 COUNTERS = {
-    "source_sha256": "d7ba44e196b2ad473954b0ed2b7611c60ef2d393999d26e5d4d33e69b8e8252b",
+    "source_sha256": "3aea86a059c84044884a980cefec57624bdbc3abda8190cd0718b49fcd385090",
     "workload": "lj_fluid_4m",
     "persistent_f32_lean": {
         "hbm_read_bytes_per_atom_step": 254.0, "hbm_write_bytes_per_atom_step": 80.7,
         "valu_fp32_flop_per_atom_step": 2351.9, "valu_fp64_flop_per_atom_step": 54.5,
         "mfma_f32_flop_per_atom_step": 3773.2, "valu_instructions_per_cell_step": 1108.0,
-        "valu_pipe_busy": 0.742, "l2_hit_rate": 0.361, "lds_conflict_cycles_per_lds_cycle": 1.666,
+        "valu_pipe_busy": 0.744, "l2_hit_rate": 0.361, "lds_conflict_cycles_per_lds_cycle": 1.666,
         "profile": "profiles/persistent_f32_lean_lj_fluid_4m.md"},
     "persistent_f64_lean": {
-        "hbm_read_bytes_per_atom_step": 312.9, "hbm_write_bytes_per_atom_step": 65.2,
+        "hbm_read_bytes_per_atom_step": 312.8, "hbm_write_bytes_per_atom_step": 65.2,
         "valu_fp32_flop_per_atom_step": 107.1, "valu_fp64_flop_per_atom_step": 3656.8,
         "mfma_f32_flop_per_atom_step": 3773.2, "valu_instructions_per_cell_step": 1704.0,
         "valu_pipe_busy": 0.57, "l2_hit_rate": 0.397, "lds_conflict_cycles_per_lds_cycle": 0.499,
