@@ -303,6 +303,34 @@ def slab_leg(steps=2000, trace_steps=100):
     return out
 
 
+def thermostat_leg(sysm, stream, steps=100, warmup=20):
+    """Per-slice velocity-scaling thermostat (NVT) runs of `sysm` at its own temperature, both
+    precisions: ms per step of one `steps`-step launch after `warmup` steps, and the kinetic
+    temperature 2K / (3N - 3) at the end."""
+    import torch
+
+    out = {"steps": steps, "warmup": warmup, "T0": sysm.meta["T"]}
+    for name, prec in (("fp32_force", md.MD_FP32_FORCE), ("fp64", md.MD_FP64)):
+        with md.Sim(sysm.box, sysm.slices, sysm.rc, sysm.dt, prec) as sim:
+            sim.set_stream(stream.cuda_stream)
+            sim.set_option(md.OPT_MAX_STEPS_PER_LAUNCH, steps)
+            sim.set_thermostat(sysm.meta["T"])
+            sim.load(sysm.pos, sysm.vel)
+            sim.step(warmup)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            sim.step(steps)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / steps
+            _, K, _ = sim.energy_virial()
+            out[name] = {"ms_per_step": ms, "atom_steps_per_s": sysm.n / (1e-3 * ms),
+                         "T_end": 2.0 * K / (3.0 * sysm.n - 3.0)}
+    return out
+
+
 def serve_leg(reqs, systems, budget_bytes=96 << 30, max_runs=64, label=""):
     """Open-loop replay of the given requests (arrival times of the seeded schedule)."""
     sv = md.Server(budget_bytes, max_runs)
@@ -448,6 +476,7 @@ def main():
     ap.add_argument("--no-drift", action="store_true", help="skip the precision/drift legs")
     ap.add_argument("--no-32m", action="store_true", help="skip the 33.5M-atom precision study")
     ap.add_argument("--no-slab", action="store_true", help="skip the slab leg")
+    ap.add_argument("--no-thermostat", action="store_true", help="skip the thermostat (NVT) leg")
     ap.add_argument("--quick", action="store_true",
                     help="timed legs only (no drift, 32M, slab, serving or CPU legs)")
     ap.add_argument("--fp32-only", action="store_true")
@@ -468,7 +497,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.quick:
-        args.no_drift = args.no_32m = args.no_slab = args.no_cpu_baseline = True
+        args.no_drift = args.no_32m = args.no_slab = args.no_thermostat = args.no_cpu_baseline = True
         args.serve_requests = args.small_budget_requests = 0
 
     import torch
@@ -583,6 +612,9 @@ def main():
         leg("precision_lj_liquid_32m", study32)
     if not args.no_slab:
         leg("slab_lj_slab_8m", slab_leg)
+    if not args.no_thermostat:
+        log("[bench] thermostat (NVT) runs, both precisions")
+        leg("thermostat_" + sysm.name, lambda: thermostat_leg(sysm, stream))
     if args.serve_requests > 0 or args.small_budget_requests > 0:
         reqs = inputs.served_ensemble()
         m = max(args.serve_requests, args.small_budget_requests)
