@@ -153,8 +153,9 @@ def force_errors(F, ids, oracle_out):
     return {"max": float(e.max()), "median": float(np.median(e)), "atoms": int(len(ids))}
 
 
-def timed_leg(sysm, prec, steps, warmup, stream, launch_steps, schedule=None):
-    """Warm-up, then exactly `steps` steps in one md_step call bracketed by syncs.
+def timed_leg(sysm, prec, steps, warmup, stream, launch_steps, schedule=None, repeats=2):
+    """Warm-up, then exactly `steps` steps in one md_step call bracketed by syncs (then
+    `repeats` more such windows, for the spread only).
     Every persistent launch (warm-up and timed) covers at most `launch_steps` steps.
     `schedule`: optional (claim order, wavefront levels, XCD queues) for scheduler studies."""
     import torch
@@ -181,7 +182,16 @@ def timed_leg(sysm, prec, steps, warmup, stream, launch_steps, schedule=None):
     wall = time.perf_counter() - t0
     st = sim.stats()
     ev_s = ev0.elapsed_time(ev1) * 1e-3
-    # pair statistics at the end of the timed window (candidates C, in-range P per atom-step)
+    # the same window twice more, continuing the trajectory (for the spread only: the
+    # reported throughput is the first window's)
+    times = [ev_s]
+    for _ in range(repeats):
+        ev0.record(stream)
+        sim.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1) * 1e-3)
+    # pair statistics at the end of the timed windows (candidates C, in-range P per atom-step)
     sim.set_option(md.OPT_COUNT_PAIRS, 1)
     sim.step(2)
     cs = sim.stats()
@@ -190,7 +200,7 @@ def timed_leg(sysm, prec, steps, warmup, stream, launch_steps, schedule=None):
     sim.close()
     return {"wall_s": wall, "event_s": ev_s, "kernel_s": st.last_kernel_seconds,
             "launches": st.last_launches, "grid": st.persistent_grid, "chunks": st.chunks_per_slice,
-            "C": C, "P": P}
+            "C": C, "P": P, "repeat_event_s": times}
 
 
 def run_with_samples(sysm, prec, steps, every, ids=None, oracle_t0=None, miglog=False):
@@ -300,6 +310,60 @@ def slab_leg(steps=2000, trace_steps=100):
     chk = tracecheck.check(rec, s.slices)
     out["utilisation"] = {"steps": trace_steps, "workers": st.persistent_grid, **u,
                           "races": len(chk["violations"])}
+    return out
+
+
+def system_info():
+    """ROCm version and rocm-smi's clocks and power cap (whatever of it the box reports).
+    Runs child processes, so it is called before anything initialises the GPU."""
+    import subprocess
+
+    env = {}
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            env["rocm"] = f.read().strip()
+    except OSError:
+        env["rocm"] = None
+    for key, flag in (("clocks", "--showclocks"), ("power_cap", "--showmaxpower")):
+        try:
+            r = subprocess.run(["rocm-smi", flag, "--json"], capture_output=True, text=True, timeout=30)
+            env[key] = json.loads(r.stdout) if r.returncode == 0 and r.stdout.strip() else None
+        except (OSError, ValueError, subprocess.SubprocessError):
+            env[key] = None
+    return env
+
+
+def environment(sysinfo):
+    """GPU model and architecture, HIP / torch versions, plus `system_info()`."""
+    import torch
+
+    pr = torch.cuda.get_device_properties(0)
+    return {"gpu": torch.cuda.get_device_name(0), "arch": getattr(pr, "gcnArchName", None),
+            "compute_units": pr.multi_processor_count, "hbm_bytes": pr.total_memory,
+            "torch": torch.__version__, "hip": torch.version.hip, **sysinfo}
+
+
+def sampling_leg(sysm, stream, steps=200, launch_steps=100, warmup=20):
+    """FP32-force ms per step with energy samples every 100 and every 10 steps (a launch runs
+    all its steps in the kernel variant its sampled steps need)."""
+    import torch
+
+    out = {"steps": steps, "steps_per_launch": launch_steps}
+    for every in (100, 10):
+        with md.Sim(sysm.box, sysm.slices, sysm.rc, sysm.dt, md.MD_FP32_FORCE) as sim:
+            sim.set_stream(stream.cuda_stream)
+            sim.set_option(md.OPT_MAX_STEPS_PER_LAUNCH, launch_steps)
+            sim.set_option(md.OPT_ENERGY_EVERY, every)
+            sim.load(sysm.pos, sysm.vel)
+            sim.step(warmup)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            sim.step(steps)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            out[f"every_{every}_ms_per_step"] = ev0.elapsed_time(ev1) / steps
     return out
 
 
@@ -477,6 +541,7 @@ def main():
     ap.add_argument("--no-32m", action="store_true", help="skip the 33.5M-atom precision study")
     ap.add_argument("--no-slab", action="store_true", help="skip the slab leg")
     ap.add_argument("--no-thermostat", action="store_true", help="skip the thermostat (NVT) leg")
+    ap.add_argument("--no-sampling", action="store_true", help="skip the energy-sampling leg")
     ap.add_argument("--quick", action="store_true",
                     help="timed legs only (no drift, 32M, slab, serving or CPU legs)")
     ap.add_argument("--fp32-only", action="store_true")
@@ -493,12 +558,15 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the slice-streaming path is built and measured "
-              "on one MI355X; multi-GPU sharding is described in DESIGN.md but not built.",
+              "on one MI355X; sharding over several GPUs is designed but not built.",
               file=sys.stderr)
         sys.exit(2)
     if args.quick:
-        args.no_drift = args.no_32m = args.no_slab = args.no_thermostat = args.no_cpu_baseline = True
+        args.no_drift = args.no_32m = args.no_slab = args.no_thermostat = args.no_sampling = True
+        args.no_cpu_baseline = True
         args.serve_requests = args.small_budget_requests = 0
+    # (child processes only before the GPU is initialised)
+    sysinfo = {} if args.quick else system_info()
 
     import torch
 
@@ -526,7 +594,8 @@ def main():
         if args.fp32_only and prec == md.MD_FP64:
             continue
         log(f"[bench] timed leg {name}: warmup {args.warmup}, steps {args.steps}")
-        legs[name] = timed_leg(sysm, prec, args.steps, args.warmup, stream, args.launch_steps, schedule)
+        legs[name] = timed_leg(sysm, prec, args.steps, args.warmup, stream, args.launch_steps, schedule,
+                               repeats=0 if args.quick else 2)
         log(f"[bench]   {legs[name]}")
 
     main_leg = legs["fp32_force"]
@@ -579,6 +648,8 @@ def main():
             "unpacked_fp32_ceiling_frac": 0.5,
         },
     }
+    out["repeat_ms_per_step"] = [1e3 * t / args.steps for t in main_leg["repeat_event_s"]]
+    out["median_ms_per_step"] = 1e3 * float(np.median(main_leg["repeat_event_s"])) / args.steps
     if "fp64" in legs:
         f = legs["fp64"]
         v64 = n * args.steps / f["event_s"]
@@ -590,6 +661,7 @@ def main():
                                                   n * args.steps / max(f["launches"], 1),
                                                   f["kernel_s"] / max(f["launches"], 1))}
         out["fp32_force_speedup_vs_fp64"] = value / v64
+        out["fp64"]["repeat_ms_per_step"] = [1e3 * t / args.steps for t in f["repeat_event_s"]]
 
     def leg(name, fn):
         try:
@@ -612,6 +684,9 @@ def main():
         leg("precision_lj_liquid_32m", study32)
     if not args.no_slab:
         leg("slab_lj_slab_8m", slab_leg)
+    if not args.no_sampling:
+        log("[bench] energy sampling every 100 and every 10 steps (FP32 forces)")
+        leg("sampling_" + sysm.name, lambda: sampling_leg(sysm, stream))
     if not args.no_thermostat:
         log("[bench] thermostat (NVT) runs, both precisions")
         leg("thermostat_" + sysm.name, lambda: thermostat_leg(sysm, stream))
@@ -634,6 +709,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         leg("cpu_baseline", lambda: cpu_baseline(sysm))
+    leg("environment", lambda: environment(sysinfo))
     print(json.dumps(out), flush=True)
 
 

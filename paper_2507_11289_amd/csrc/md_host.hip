@@ -1071,7 +1071,8 @@ static int plan_queues(md_sim* s) {
 static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& ksteps, LaunchScratch& ls,
                          hipStream_t st, int64_t grid_override, int64_t watchdog_ms, int* last_grid,
                          std::vector<int>& status, double* kernel_seconds = nullptr,
-                         md_sim* trace_owner = nullptr, uint32_t launch_index = 0, Carve* arena = nullptr) {
+                         md_sim* trace_owner = nullptr, uint32_t launch_index = 0, Carve* arena = nullptr,
+                         int64_t reserve_rounds = 0) {
   const size_t R = sims.size();
   status.assign(R, MD_OK);
   if (R == 0) return MD_OK;
@@ -1101,7 +1102,9 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
         !d_errs)
       return fail(MD_EINVAL, "launch scratch exhausted");
   } else {
-    if ((rc = ls.reserve(R, (size_t)nrounds))) return rc;
+    // when they grow, the round tables and the queue (below) are sized for reserve_rounds
+    // rounds if that is more, so that a longer launch later does not allocate again
+    if ((rc = ls.reserve(R, (size_t)std::max<int64_t>(nrounds, reserve_rounds)))) return rc;
     d_runs = ls.d_runs;
     d_run_prefix = ls.d_run_prefix;
     d_round_base = ls.d_round_base;
@@ -1180,9 +1183,12 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
       if (!(d_q = arena->take<unsigned long long>(total))) return fail(MD_EINVAL, "launch scratch exhausted");
     } else {
       if (total > ls.q_cap) {
+        // items of a round with every run active, times the rounds reserved beyond this launch
+        const size_t per_round = nrounds_d > 0 ? (size_t)(rb[1] - rb[0]) : 0;
+        const size_t want = total + (size_t)std::max<int64_t>(reserve_rounds - nrounds_d, 0) * per_round;
         dfree(ls.d_q);
-        if ((rc = dalloc(&ls.d_q, total))) return rc;
-        ls.q_cap = total;
+        if ((rc = dalloc(&ls.d_q, want))) return rc;
+        ls.q_cap = want;
       }
       d_q = ls.d_q;
     }
@@ -1291,13 +1297,19 @@ extern "C" int md_step(md_sim* s, int64_t nsteps) {
   std::vector<md_sim*> one(1, s);
   std::vector<int64_t> ks(1);
   std::vector<int> st;
+  // the launch buffers, when they grow, are sized for the longest launch this run may make
+  // (its steps-per-launch cap; at most a 64 MB work queue), so that stepping on after a
+  // shorter launch does not allocate
+  const int64_t queue_bytes_per_step = 8ll * s->g.S * (2ll * s->nch + finalise_items(s->nch));
+  const int64_t reserve = std::min<int64_t>(s->max_steps_per_launch,
+                                            std::max<int64_t>(1, (64ll << 20) / queue_bytes_per_step));
   while (left > 0) {
     ks[0] = std::min(left, s->max_steps_per_launch);
     // a wavefront launch holds whole rounds of wlev steps; a shorter rest runs alone
     if (s->order_kind == MD_ORDER_WAVEFRONT && ks[0] >= s->wlev) ks[0] -= ks[0] % s->wlev;
     double ksec = 0;
     int rc = packed_launch(one, ks, *s->ls, s->stream, s->grid_override, s->watchdog_ms, &s->last_grid, st,
-                           &ksec, s, (uint32_t)s->last_launches);
+                           &ksec, s, (uint32_t)s->last_launches, nullptr, reserve);
     s->last_kernel_seconds += ksec;
     s->last_launches++;
     if (!rc) rc = st[0];
