@@ -55,19 +55,19 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11289_amd", "csrc", f)
 # the kernel sources have the hash they were taken on (profiles/persistent_f32_lean_lj_fluid_4m.md,
 # profiles/persistent_f64_lean_lj_fluid_4m.md); otherwise null.
 COUNTERS = {
-    "source_sha256": "3aea86a059c84044884a980cefec57624bdbc3abda8190cd0718b49fcd385090",
+    "source_sha256": "ccaab15c788a52522e326148f098935c1dc214ee44e2c32912635a033ff2780d",
     "workload": "lj_fluid_4m",
     "persistent_f32_lean": {
         "hbm_read_bytes_per_atom_step": 254.0, "hbm_write_bytes_per_atom_step": 80.7,
         "valu_fp32_flop_per_atom_step": 2351.9, "valu_fp64_flop_per_atom_step": 54.5,
         "mfma_f32_flop_per_atom_step": 3773.2, "valu_instructions_per_cell_step": 1108.0,
-        "valu_pipe_busy": 0.744, "l2_hit_rate": 0.361, "lds_conflict_cycles_per_lds_cycle": 1.666,
+        "valu_pipe_busy": 0.743, "l2_hit_rate": 0.361, "lds_conflict_cycles_per_lds_cycle": 1.666,
         "profile": "profiles/persistent_f32_lean_lj_fluid_4m.md"},
     "persistent_f64_lean": {
-        "hbm_read_bytes_per_atom_step": 312.8, "hbm_write_bytes_per_atom_step": 65.2,
+        "hbm_read_bytes_per_atom_step": 313.4, "hbm_write_bytes_per_atom_step": 65.2,
         "valu_fp32_flop_per_atom_step": 107.1, "valu_fp64_flop_per_atom_step": 3656.8,
         "mfma_f32_flop_per_atom_step": 3773.2, "valu_instructions_per_cell_step": 1704.0,
-        "valu_pipe_busy": 0.57, "l2_hit_rate": 0.397, "lds_conflict_cycles_per_lds_cycle": 0.499,
+        "valu_pipe_busy": 0.57, "l2_hit_rate": 0.396, "lds_conflict_cycles_per_lds_cycle": 0.499,
         "profile": "profiles/persistent_f64_lean_lj_fluid_4m.md"},
 }
 
@@ -153,9 +153,25 @@ def force_errors(F, ids, oracle_out):
     return {"max": float(e.max()), "median": float(np.median(e)), "atoms": int(len(ids))}
 
 
-def timed_leg(sysm, prec, steps, warmup, stream, launch_steps, schedule=None, repeats=2):
-    """Warm-up, then exactly `steps` steps in one md_step call bracketed by syncs (then
-    `repeats` more such windows, for the spread only).
+def gpu_preheat(seconds=0.5):
+    """Untimed FP32 matrix products for `seconds`, before any timed leg: an idle GPU runs at
+    a low clock, and the first short timed window would otherwise measure its ramp-up."""
+    import torch
+
+    a = torch.randn(4096, 4096, device="cuda")
+    b = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            a = torch.mm(a, b) * 1e-3
+        torch.cuda.synchronize()
+    del a, b
+
+
+def timed_leg(sysm, prec, steps, warmup, stream, launch_steps, schedule=None, repeats=2, preheat=0.0):
+    """Load, `preheat` seconds of `gpu_preheat`, warm-up, then exactly `steps` steps in one
+    md_step call bracketed by syncs (then `repeats` more such windows, for the spread only).
     Every persistent launch (warm-up and timed) covers at most `launch_steps` steps.
     `schedule`: optional (claim order, wavefront levels, XCD queues) for scheduler studies."""
     import torch
@@ -169,6 +185,8 @@ def timed_leg(sysm, prec, steps, warmup, stream, launch_steps, schedule=None, re
         sim.set_option(md.OPT_WAVEFRONT_LEVELS, levels)
         sim.set_option(md.OPT_XCD_QUEUES, xcd)
     sim.load(sysm.pos, sysm.vel)
+    if preheat > 0:
+        gpu_preheat(preheat)
     if warmup:
         sim.step(warmup)
     torch.cuda.synchronize()
@@ -595,7 +613,7 @@ def main():
             continue
         log(f"[bench] timed leg {name}: warmup {args.warmup}, steps {args.steps}")
         legs[name] = timed_leg(sysm, prec, args.steps, args.warmup, stream, args.launch_steps, schedule,
-                               repeats=0 if args.quick else 2)
+                               repeats=0 if args.quick else 2, preheat=0.0 if args.quick else 0.5)
         log(f"[bench]   {legs[name]}")
 
     main_leg = legs["fp32_force"]
