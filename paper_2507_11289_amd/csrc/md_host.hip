@@ -891,7 +891,7 @@ static void launch_samples(const md_sim* s, int64_t k_steps, int64_t* nsample, i
 // Per-run preparation of a launch of k steps: claim table, energy/migration buffers
 // (the run's own, or carved from `arena`), and the device-visible RunArgs.
 static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st, RunArgs* ra,
-                       int64_t* nsample_out, int64_t* first_j_out, Carve* arena) {
+                       int64_t* nsample_out, int64_t* first_j_out, Carve* arena, int64_t reserve_steps = 0) {
   const DGeom& g = s->g;
   int rc;
   // claim table of one round: wlev steps of the wavefront (as many as this launch holds),
@@ -920,15 +920,21 @@ static int prepare_run(md_sim* s, int64_t k_steps, bool dataflow, hipStream_t st
     s->cur_miglog = arena->take<uint32_t>(ml);
     if (!s->cur_epart || !s->cur_miglog) return fail(MD_EINVAL, "launch scratch exhausted");
   } else {
+    // when they grow, sized for a launch of reserve_steps steps if that is more (at most
+    // reserve_steps / every + 1 samples)
+    const int64_t rk = std::max<int64_t>(k_steps, reserve_steps);
     if (ep > s->epart_cap) {
+      const int64_t rs = s->every > 0 ? rk / s->every + 1 : 1;
+      const size_t want = std::max(ep, (size_t)rs * g.S * s->nch * 3);
       dfree(s->d_epart);
-      if ((rc = dalloc(&s->d_epart, ep))) return rc;
-      s->epart_cap = ep;
+      if ((rc = dalloc(&s->d_epart, want))) return rc;
+      s->epart_cap = want;
     }
     if (ml > s->miglog_cap) {
+      const size_t want = std::max(ml, s->miglog_on ? (size_t)rk * g.S * 2 : (size_t)1);
       dfree(s->d_miglog);
-      if ((rc = dalloc(&s->d_miglog, ml))) return rc;
-      s->miglog_cap = ml;
+      if ((rc = dalloc(&s->d_miglog, want))) return rc;
+      s->miglog_cap = want;
     }
     s->cur_epart = s->d_epart;
     s->cur_miglog = s->d_miglog;
@@ -1122,7 +1128,8 @@ static int packed_launch(std::vector<md_sim*>& sims, std::vector<int64_t>& kstep
   const int mode = sims[idx[0]]->order_kind == MD_ORDER_DATAFLOW ? 0 : 1;
   for (size_t q = 0; q < R; q++) {
     md_sim* s = sims[idx[q]];
-    if ((rc = prepare_run(s, ksteps[idx[q]], mode == 0, st, &ra[q], &nsample[idx[q]], &first_j[idx[q]], arena)))
+    if ((rc = prepare_run(s, ksteps[idx[q]], mode == 0, st, &ra[q], &nsample[idx[q]], &first_j[idx[q]], arena,
+                          reserve_rounds)))
       return rc;
     prefix[q + 1] = prefix[q] + ra[q].ips;
     max_slices = std::max(max_slices, s->g.S);

@@ -547,9 +547,10 @@ def test_torch_caching_allocator_gives_the_same_trajectory(c0):
 
 
 def test_longer_launch_after_a_shorter_one_allocates_nothing(c0):
-    """When its launch buffers (work queue, round tables) grow, md_step sizes them for the
-    longest launch the run may make (its steps-per-launch cap): after a 5-step launch,
-    20-step launches allocate no device memory (counted through md_set_allocator)."""
+    """When its launch buffers (work queue, round tables, energy partials, migration log)
+    grow, md_step sizes them for the longest launch the run may make (its steps-per-launch
+    cap): after a 5-step launch, 20-step launches allocate no device memory (counted
+    through md_set_allocator), without and with energy samples and the migration log."""
     import torch
     say("[gpu] no allocation when a longer launch follows a shorter one")
     torch.cuda.init()
@@ -561,14 +562,18 @@ def test_longer_launch_after_a_shorter_one_allocates_nothing(c0):
 
     md.set_allocator(alloc, lambda p: torch.cuda.caching_allocator_delete(p))
     try:
-        with md.Sim(c0.box, c0.slices, c0.rc, c0.dt, md.MD_FP32_FORCE) as sim:
-            sim.set_option(md.OPT_MAX_STEPS_PER_LAUNCH, 100)
-            sim.load(c0.pos, c0.vel)
-            sim.step(5)
-            before = len(sizes)
-            sim.step(20)
-            sim.step(20)
-            assert len(sizes) == before, sizes[before:]
+        for every, miglog in ((0, 0), (5, 1)):
+            with md.Sim(c0.box, c0.slices, c0.rc, c0.dt, md.MD_FP32_FORCE) as sim:
+                sim.set_option(md.OPT_MAX_STEPS_PER_LAUNCH, 100)
+                if every:
+                    sim.set_option(md.OPT_ENERGY_EVERY, every)
+                sim.set_option(md.OPT_MIGRATION_LOG, miglog)
+                sim.load(c0.pos, c0.vel)
+                sim.step(5)
+                before = len(sizes)
+                sim.step(20)
+                sim.step(20)
+                assert len(sizes) == before, (every, miglog, sizes[before:])
     finally:
         md.set_allocator(None, None)
 
