@@ -55,19 +55,19 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11289_amd", "csrc", f)
 # the kernel sources have the hash they were taken on (profiles/persistent_f32_lean_lj_fluid_4m.md,
 # profiles/persistent_f64_lean_lj_fluid_4m.md); otherwise null.
 COUNTERS = {
-    "source_sha256": "ccaab15c788a52522e326148f098935c1dc214ee44e2c32912635a033ff2780d",
+    "source_sha256": "6e1a6751995e5111032a9a1963a3a853e5d5cd26b321a83a85619fcdc6d77bcf",
     "workload": "lj_fluid_4m",
     "persistent_f32_lean": {
-        "hbm_read_bytes_per_atom_step": 254.0, "hbm_write_bytes_per_atom_step": 80.7,
+        "hbm_read_bytes_per_atom_step": 254.1, "hbm_write_bytes_per_atom_step": 80.7,
         "valu_fp32_flop_per_atom_step": 2351.9, "valu_fp64_flop_per_atom_step": 54.5,
         "mfma_f32_flop_per_atom_step": 3773.2, "valu_instructions_per_cell_step": 1108.0,
-        "valu_pipe_busy": 0.743, "l2_hit_rate": 0.361, "lds_conflict_cycles_per_lds_cycle": 1.666,
+        "valu_pipe_busy": 0.748, "l2_hit_rate": 0.36, "lds_conflict_cycles_per_lds_cycle": 1.666,
         "profile": "profiles/persistent_f32_lean_lj_fluid_4m.md"},
     "persistent_f64_lean": {
-        "hbm_read_bytes_per_atom_step": 313.4, "hbm_write_bytes_per_atom_step": 65.2,
+        "hbm_read_bytes_per_atom_step": 313.1, "hbm_write_bytes_per_atom_step": 65.2,
         "valu_fp32_flop_per_atom_step": 107.1, "valu_fp64_flop_per_atom_step": 3656.8,
         "mfma_f32_flop_per_atom_step": 3773.2, "valu_instructions_per_cell_step": 1704.0,
-        "valu_pipe_busy": 0.57, "l2_hit_rate": 0.396, "lds_conflict_cycles_per_lds_cycle": 0.499,
+        "valu_pipe_busy": 0.571, "l2_hit_rate": 0.397, "lds_conflict_cycles_per_lds_cycle": 0.499,
         "profile": "profiles/persistent_f64_lean_lj_fluid_4m.md"},
 }
 
